@@ -1,0 +1,214 @@
+/*
+ * uoi.h -- C ABI of the MI355X (gfx950) UoI_LASSO / UoI_VAR library (libuoi.so).
+ *
+ * Method: Union of Intersections LASSO and its vector-autoregressive variant,
+ * arXiv 1808.06992 (Algorithm 1, Algorithm 2).  Model selection solves a LASSO
+ * (Eq. (2)) for every bootstrap k = 1..B1 and every lambda_j, j = 1..q, with ADMM
+ * (Eq. (ADMM), Sec. II-E); the supports are intersected over bootstraps
+ * (Eq. (intersection)); model estimation refits every support by least squares
+ * on B2 training/evaluation splits, keeps the best support per split and
+ * averages the refits (Eq. (union)).
+ *
+ * Conventions shared by every entry point
+ *  - Every array argument is a DEVICE pointer (hipMalloc'd or a torch CUDA
+ *    tensor) on the HIP device that is current in the calling thread, unless the
+ *    comment says HOST.  Matrices are row-major, float64, densely packed.
+ *  - The caller owns every input and output buffer; the library never frees or
+ *    keeps a pointer to them.  Scratch memory is allocated by the library itself
+ *    (a grow-only pool per device, released by uoi_release_workspace).
+ *  - Work is enqueued on opts->stream (a hipStream_t; NULL = the default
+ *    stream).  The fit and solve entry points synchronise that stream before
+ *    returning, so outputs are valid on return.
+ *  - Return value: UOI_OK (0) or a negative code.  No C++ exception crosses the
+ *    ABI.  On error, uoi_last_error() returns a message (thread-local).
+ *    Argument validation (sizes, lambda ordering, NaN/Inf in the data) happens
+ *    before any result is written.  UOI_ENOCONV means every output was written
+ *    but at least one ADMM solve did not reach opts->kkt_tol within max_iter;
+ *    the per-solve flags in uoi_diag say which.
+ *  - Objective scaling: for a sample of m rows the LASSO minimised is
+ *        (1/(2m)) * sum_rows (y - x'b)^2 + lambda * ||b||_1,
+ *    which has the same minimiser as Eq. (2) with penalty 2*m*lambda.  Lambdas
+ *    are given in this scaling and must be strictly decreasing and >= 0.
+ *  - KKT residual (the stopping rule and the reported accuracy): with
+ *    G = X'X/m, c = X'y/m and g = c - G b,
+ *        v_i = |g_i - lambda*sign(b_i)|   if b_i != 0,
+ *        v_i = max(0, |g_i| - lambda)    if b_i == 0,
+ *        kkt = ||v||_inf / ||c||_inf.
+ *    It is always evaluated in float64 with the float64 Gram.
+ *  - Not thread-safe: calls that overlap on one device must be serialised by
+ *    the caller.
+ */
+#ifndef UOI_H
+#define UOI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    UOI_OK = 0,
+    UOI_EINVAL = -1,  /* invalid argument (nothing was written)                */
+    UOI_ENOMEM = -2,  /* device allocation failed                              */
+    UOI_EHIP = -3,    /* a HIP runtime call or kernel launch failed            */
+    UOI_ENOCONV = -4  /* outputs written; some solves missed the KKT tolerance */
+};
+
+/* precision of the selection sweep */
+enum {
+    UOI_FP64 = 0,   /* float64 Gram, factor, ADMM and KKT                        */
+    UOI_MIXED = 1   /* float64 Gram and factor, float32 ADMM state and operator,
+                       float64 KKT checks and float64 finishing iterations        */
+};
+
+/* ADMM warm start */
+enum {
+    UOI_COLD = 0,   /* z = u = 0                                                 */
+    UOI_MLP = 1     /* (z, u) predicted by the loaded warm-start network          */
+};
+
+/* selection solver organisation */
+enum {
+    UOI_SOLVER_BATCHED = 0, /* per bootstrap, all lambdas (and VAR equations) of one
+                               ADMM iteration form one matrix product              */
+    UOI_SOLVER_PLAIN = 1    /* one solve per workgroup, matrix-vector products     */
+};
+
+/* opts.flags */
+#define UOI_FLAG_TIMING 1u  /* fill uoi_diag.stage_ms with hipEvent stage times */
+
+typedef struct uoi_opts {
+    int32_t B1;            /* selection bootstraps, >= 1                                   */
+    int32_t B2;            /* estimation splits, >= 1                                      */
+    int32_t q;             /* number of lambdas, >= 1                                      */
+    const double *lambdas; /* HOST, q values, strictly decreasing, >= 0                    */
+    uint64_t seed;         /* drives every random choice (bootstrap rows, splits, blocks)  */
+    double rho;            /* ADMM penalty, > 0 (default 1)                                */
+    double kkt_tol;        /* relative KKT tolerance, > 0 (default 1e-6)                   */
+    int32_t max_iter;      /* ADMM iteration cap, >= 1 (default 20000)                     */
+    int32_t check_every;   /* KKT check period in ADMM iterations, >= 1 (default 10)       */
+    int32_t train_num;     /* estimation split: train = floor(m*train_num/train_den) rows  */
+    int32_t train_den;     /*   (LASSO) or blocks (VAR); default 4/5                       */
+    int32_t precision;     /* UOI_FP64 or UOI_MIXED                                        */
+    int32_t warm_start;    /* UOI_COLD or UOI_MLP                                          */
+    int32_t solver;        /* UOI_SOLVER_BATCHED or UOI_SOLVER_PLAIN                       */
+    uint32_t flags;        /* UOI_FLAG_*                                                   */
+    void *stream;          /* hipStream_t, NULL = default stream                           */
+} uoi_opts;
+
+/* Optional diagnostics.  Array members are DEVICE pointers owned by the caller
+ * and may be NULL; scalar members are written by the library.  A selection
+ * solve is indexed s = k*R + r, with R = q for LASSO and R = q*p for VAR
+ * (r = j*p + e, e = equation). */
+typedef struct uoi_diag {
+    int32_t *iters;     /* [B1*R] ADMM iterations at convergence (-1 = not converged)   */
+    double *kkt;        /* [B1*R] final float64 relative KKT residual                    */
+    double *sel_beta;   /* [B1*R*p] selection estimates z, solve-major                   */
+    double *losses;     /* [B2*q] estimation losses (VAR: summed over equations)         */
+    int64_t n_solves;   /* B1*R                                                          */
+    int64_t n_unconverged;
+    int32_t max_iters;  /* largest iteration count among converged solves               */
+    float stage_ms[8];  /* with UOI_FLAG_TIMING: index/gram, factor, admm, verify,
+                           support, estimation-gram, ols, loss+average                   */
+} uoi_diag;
+
+/* Fill *o with the defaults listed above (B1 = B2 = q = 0, lambdas = NULL). */
+void uoi_default_opts(uoi_opts *o);
+
+/*
+ * UoI_LASSO, Algorithm 1.
+ *   n, p      rows and features (n >= 2, p >= 1)
+ *   X         n*p row-major design; y: n responses
+ *   beta_out  [p]   averaged estimate beta* (Eq. (union))
+ *   supp_out  [q*W] intersected supports S_j (Eq. (intersection)), W = ceil(p/64)
+ *             uint64 words, bit i of word i/64 set when feature i is in S_j
+ *   jstar_out [B2]  support index chosen by each estimation split
+ *   diag      nullable
+ */
+int uoi_lasso_fit(int32_t n, int32_t p, const double *X, const double *y, const uoi_opts *o,
+                  double *beta_out, uint64_t *supp_out, int32_t *jstar_out, uoi_diag *diag);
+
+/*
+ * UoI_VAR, Algorithm 2, for a VAR(d) series (Eq. (5)); d = 1 is supported.
+ * The lag-1 regression of Eq. (6)-(7) uses rows t = 1..T-1 (response X_t,
+ * design X_{t-1}).  The vectorised LASSO of Eq. (8) is solved as p per-equation
+ * LASSOs that share the design Gram and one lambda (the Kronecker matrix of
+ * Eq. (8) is never formed).
+ *   T, p       series length (T >= 3) and dimension (p >= 1); d must be 1
+ *   series     T*p row-major, time ascending
+ *   block_len  bootstrap block length in regression rows; 0 = smallest L with
+ *              L^3 >= T-1
+ *   A_out      [p*p] A_1 estimate, A[i][l] = coefficient of x_{t-1,l} in equation i
+ *   mu_out     [p]   intercept estimate (the model has none: written as zeros)
+ *   supp_out   [q*p*W] supports S_j per equation, W = ceil(p/64)
+ *   jstar_out  [B2]  support index chosen per split (one for all equations)
+ */
+int uoi_var_fit(int32_t T, int32_t p, int32_t d, const double *series, int32_t block_len,
+                const uoi_opts *o, double *A_out, double *mu_out, uint64_t *supp_out,
+                int32_t *jstar_out, uoi_diag *diag);
+
+/*
+ * Batch of LASSO solves by ADMM (the selection inner loop, Eq. (ADMM)) for nb
+ * problems given by their normal-equation statistics, each at all q lambdas.
+ *   G    [nb*p*p]  symmetric positive definite Grams
+ *   c    [nb*p]    linear terms
+ *   z0   [nb*q*p]  nullable warm start for z (u starts at 0 unless u0 given)
+ *   u0   [nb*q*p]  nullable warm start for u
+ *   z_out, u_out [nb*q*p] final iterates (u_out nullable), solve-major
+ *   iters [nb*q], kkt [nb*q]  nullable per-solve diagnostics
+ * opts: q, lambdas, rho, kkt_tol, max_iter, check_every, precision, solver, stream
+ * are used; B1/B2/seed are ignored.
+ */
+int uoi_lasso_solve_batch(int32_t nb, int32_t p, const double *G, const double *c,
+                          const uoi_opts *o, const double *z0, const double *u0,
+                          double *z_out, double *u_out, int32_t *iters, double *kkt);
+
+/*
+ * Gram of sampled rows (Alg. 1 bootstrap statistics): for b < nb,
+ *   G_b = X_r'X_r / m,  C_b = X_r'Y_r / m  with r = rows[b*m .. b*m+m-1]
+ * (rows counted with multiplicity), X row r at X + r*ldx (p values), Y row r at
+ * Y + r*ldy (pe values).  G [nb*p*p], C [nb*p*pe] (nullable when pe == 0).
+ */
+int uoi_gram(int32_t nb, int32_t m, const int32_t *rows, int32_t p, const double *X,
+             int32_t ldx, int32_t pe, const double *Y, int32_t ldy, double *G, double *C,
+             void *stream);
+
+/*
+ * Index streams (device output; host-callable for tests).  Counter-based
+ * SplitMix64 keys key(seed, tag, k, i) mapped to [0, m) by multiply-shift.
+ *   uoi_bootstrap_rows:  rows[k*n + i] for k < nb: n draws with replacement
+ *   uoi_split_rows:      train[k*ntr..], eval[k*(n-ntr)..], ascending, with
+ *                        ntr = floor(n*num/den)
+ *   uoi_var_boot_rows:   rows[k*N + i]: moving blocks of length L
+ *   uoi_var_split_rows:  blocks split by key; train/eval rows ascending;
+ *                        counts written to HOST ntr_out[nb], nev_out[nb];
+ *                        train/eval rows at offsets k*N
+ */
+int uoi_bootstrap_rows(uint64_t seed, int32_t nb, int32_t n, int32_t *rows, void *stream);
+int uoi_split_rows(uint64_t seed, int32_t nb, int32_t n, int32_t num, int32_t den,
+                   int32_t *train, int32_t *eval, void *stream);
+int uoi_var_boot_rows(uint64_t seed, int32_t nb, int32_t N, int32_t L, int32_t *rows,
+                      void *stream);
+int uoi_var_split_rows(uint64_t seed, int32_t nb, int32_t N, int32_t L, int32_t num,
+                       int32_t den, int32_t *train, int32_t *eval, int32_t *ntr_out,
+                       int32_t *nev_out, void *stream);
+
+/* Batched inverse of G_b + rho*I (float64, blocked Gauss-Jordan sweep):
+ * M [nb*p*p] may alias nothing else.  Used by the ADMM x-update. */
+int uoi_spd_inverse(int32_t nb, int32_t p, const double *G, double rho, double *M, void *stream);
+
+/* Free the library's scratch pool on the current device. */
+void uoi_release_workspace(void);
+
+/* Message for the last non-OK status returned in this thread ("" if none). */
+const char *uoi_last_error(void);
+
+/* Library version string. */
+const char *uoi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* UOI_H */

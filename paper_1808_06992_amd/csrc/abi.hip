@@ -1,0 +1,554 @@
+// C ABI of libuoi: argument validation, scratch pool, and the orchestration of
+// UoI_LASSO (Alg. 1) and UoI_VAR (Alg. 2) over the device kernels.  Every step
+// of the fit runs in this library's kernels; the host only validates, sizes
+// scratch memory, launches, and reads back small control values (convergence
+// counts, support sizes).
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+namespace uoi {
+
+static thread_local std::string g_last_error;
+void set_last_error(const std::string &m) { g_last_error = m; }
+
+// ---------------------------------------------------------------------------
+// grow-only scratch pool, one per device
+// ---------------------------------------------------------------------------
+namespace {
+struct PoolEntry {
+    void *ptr = nullptr;
+    size_t cap = 0;
+};
+std::mutex g_pool_mu;
+std::map<int, PoolEntry> g_pool;
+}  // namespace
+
+void *pool_get(size_t bytes) {
+    int dev = 0;
+    UOI_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    PoolEntry &e = g_pool[dev];
+    if (e.cap < bytes) {
+        if (e.ptr) {
+            UOI_HIP(hipDeviceSynchronize());
+            UOI_HIP(hipFree(e.ptr));
+            e.ptr = nullptr;
+            e.cap = 0;
+        }
+        size_t want = bytes + bytes / 8 + (1 << 20);
+        hipError_t err = hipMalloc(&e.ptr, want);
+        if (err != hipSuccess) {
+            e.ptr = nullptr;
+            (void)hipGetLastError();
+            throw Error(UOI_ENOMEM, "scratch allocation of " + std::to_string(want) + " bytes failed");
+        }
+        e.cap = want;
+    }
+    return e.ptr;
+}
+
+void pool_release() {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    auto it = g_pool.find(dev);
+    if (it != g_pool.end() && it->second.ptr) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(it->second.ptr);
+        it->second = PoolEntry{};
+    }
+}
+
+// ---------------------------------------------------------------------------
+// validation helpers
+// ---------------------------------------------------------------------------
+static void check_opts(const uoi_opts *o, bool need_boot) {
+    UOI_REQUIRE(o != nullptr, "opts is NULL");
+    if (need_boot) {
+        UOI_REQUIRE(o->B1 >= 1, "B1 must be >= 1");
+        UOI_REQUIRE(o->B2 >= 1, "B2 must be >= 1");
+        UOI_REQUIRE(o->train_den > 0 && o->train_num > 0 && o->train_num < o->train_den,
+                    "train_num/train_den must be a fraction in (0, 1)");
+    }
+    UOI_REQUIRE(o->q >= 1, "q must be >= 1");
+    UOI_REQUIRE(o->lambdas != nullptr, "lambdas is NULL");
+    for (int j = 0; j < o->q; ++j) {
+        UOI_REQUIRE(std::isfinite(o->lambdas[j]) && o->lambdas[j] >= 0.0,
+                    "lambdas must be finite and >= 0");
+        if (j) UOI_REQUIRE(o->lambdas[j] < o->lambdas[j - 1], "lambdas must be strictly decreasing");
+    }
+    UOI_REQUIRE(std::isfinite(o->rho) && o->rho > 0.0, "rho must be > 0");
+    UOI_REQUIRE(std::isfinite(o->kkt_tol) && o->kkt_tol > 0.0, "kkt_tol must be > 0");
+    UOI_REQUIRE(o->max_iter >= 1, "max_iter must be >= 1");
+    UOI_REQUIRE(o->check_every >= 1, "check_every must be >= 1");
+    UOI_REQUIRE(o->precision == UOI_FP64 || o->precision == UOI_MIXED, "unknown precision");
+    UOI_REQUIRE(o->warm_start == UOI_COLD, "warm start by network: no network loaded");
+    UOI_REQUIRE(o->solver == UOI_SOLVER_BATCHED || o->solver == UOI_SOLVER_PLAIN, "unknown solver");
+}
+
+static void check_finite(hipStream_t s, const double *x, size_t n, const char *what) {
+    int *flag = nullptr;
+    UOI_HIP(hipMalloc(&flag, sizeof(int)));
+    int h = 0;
+    try {
+        UOI_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
+        launch_finite_check(s, x, n, flag);
+        UOI_HIP(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+        UOI_HIP(hipStreamSynchronize(s));
+    } catch (...) {
+        (void)hipFree(flag);
+        throw;
+    }
+    UOI_HIP(hipFree(flag));
+    if (h) throw Error(UOI_EINVAL, std::string(what) + " contains NaN or Inf");
+}
+
+// z in [nb][p][R] (feature-major) <-> [nb][R][p] (solve-major)
+__global__ void k_transpose(int nb, int p, int R, const double *__restrict__ a, double *__restrict__ b,
+                            int to_solve_major) {
+    __shared__ double t[32][33];
+    int bb = blockIdx.z;
+    int x0 = blockIdx.x * 32, y0 = blockIdx.y * 32;
+    int rows = to_solve_major ? p : R, cols = to_solve_major ? R : p;
+    const double *A = a + (size_t)bb * p * R;
+    double *B = b + (size_t)bb * p * R;
+    for (int dy = threadIdx.y; dy < 32; dy += 8) {
+        int y = y0 + dy, x = x0 + threadIdx.x;
+        if (y < rows && x < cols) t[dy][threadIdx.x] = A[(size_t)y * cols + x];
+    }
+    __syncthreads();
+    for (int dy = threadIdx.y; dy < 32; dy += 8) {
+        int x = x0 + dy, y = y0 + threadIdx.x;  // out[x][y] = in[y][x]
+        if (x < cols && y < rows) B[(size_t)x * rows + y] = t[threadIdx.x][dy];
+    }
+}
+
+static void transpose(hipStream_t s, int nb, int p, int R, const double *a, double *b, bool to_solve_major) {
+    int rows = to_solve_major ? p : R, cols = to_solve_major ? R : p;
+    hipLaunchKernelGGL(k_transpose, dim3(cdiv(cols, 32), cdiv(rows, 32), nb), dim3(32, 8), 0, s, nb, p,
+                       R, a, b, to_solve_major ? 1 : 0);
+    UOI_LAUNCH_CHECK();
+}
+
+struct Timer {
+    hipStream_t s;
+    bool on;
+    std::vector<hipEvent_t> ev;
+    Timer(hipStream_t s_, bool on_) : s(s_), on(on_) {}
+    void mark() {
+        if (!on) return;
+        hipEvent_t e;
+        UOI_HIP(hipEventCreate(&e));
+        UOI_HIP(hipEventRecord(e, s));
+        ev.push_back(e);
+    }
+    float between(size_t a, size_t b) {
+        float ms = 0.f;
+        if (on && b < ev.size()) UOI_HIP(hipEventElapsedTime(&ms, ev[a], ev[b]));
+        return ms;
+    }
+    ~Timer() {
+        for (auto e : ev) (void)hipEventDestroy(e);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// UoI_LASSO
+// ---------------------------------------------------------------------------
+static int lasso_fit(int n, int p, const double *X, const double *y, const uoi_opts *o,
+                     double *beta_out, uint64_t *supp_out, int32_t *jstar_out, uoi_diag *diag) {
+    check_opts(o, true);
+    UOI_REQUIRE(n >= 2 && p >= 1, "need n >= 2 and p >= 1");
+    UOI_REQUIRE(X && y && beta_out && supp_out && jstar_out, "NULL data or output pointer");
+    const int ntr = split_count(n, o->train_num, o->train_den), nev = n - ntr;
+    UOI_REQUIRE(ntr >= 1 && nev >= 1, "estimation split leaves an empty training or evaluation set");
+    UOI_REQUIRE((int64_t)o->B1 * o->q <= (int64_t)1 << 30, "too many solves");
+    hipStream_t s = (hipStream_t)o->stream;
+    check_finite(s, X, (size_t)n * p, "X");
+    check_finite(s, y, (size_t)n, "y");
+    const bool timing = (o->flags & UOI_FLAG_TIMING) != 0;
+    float sm[8] = {0};
+
+    const int B1 = o->B1, B2 = o->B2, q = o->q, R = q;
+    AdmmProblem P{B1, p, q, 1, R, nullptr, nullptr, nullptr, o->rho, o->kkt_tol, o->max_iter,
+                  o->check_every};
+    EstimProblem E{B2, p, 1, q, R, nullptr, nullptr, nullptr, nullptr, nullptr, supp_out};
+    size_t nst = (size_t)B1 * p * R;
+    // size the scratch arena
+    Arena ar;
+    auto layout = [&](Arena &a, int32_t *&rows, double *&G, double *&c, double *&lam, double *&z,
+                      double *&u, int32_t *&its, double *&kkt, uint8_t *&flag, int32_t *&tr,
+                      int32_t *&ev, double *&GT, double *&CT, double *&GE, double *&CE, double *&sE,
+                      void *&admm_w, void *&est_w) {
+        rows = a.take<int32_t>((size_t)B1 * n);
+        G = a.take<double>((size_t)B1 * p * p);
+        c = a.take<double>((size_t)B1 * p);
+        lam = a.take<double>(q);
+        z = a.take<double>(nst);
+        u = a.take<double>(nst);
+        its = a.take<int32_t>((size_t)B1 * R);
+        kkt = a.take<double>((size_t)B1 * R);
+        flag = a.take<uint8_t>((size_t)B2 * n);
+        tr = a.take<int32_t>((size_t)B2 * ntr);
+        ev = a.take<int32_t>((size_t)B2 * nev);
+        GT = a.take<double>((size_t)B2 * p * p);
+        CT = a.take<double>((size_t)B2 * p);
+        GE = a.take<double>((size_t)B2 * p * p);
+        CE = a.take<double>((size_t)B2 * p);
+        sE = a.take<double>(B2);
+        admm_w = a.take<char>(admm_work_bytes(P, o->precision, o->solver));
+        est_w = a.take<char>(estim_work_bytes(E));
+    };
+    int32_t *rows, *its, *tr, *ev;
+    double *G, *c, *lam, *z, *u, *kkt, *GT, *CT, *GE, *CE, *sE;
+    uint8_t *flag;
+    void *admm_w, *est_w;
+    layout(ar, rows, G, c, lam, z, u, its, kkt, flag, tr, ev, GT, CT, GE, CE, sE, admm_w, est_w);
+    Arena A;
+    A.cap = ar.off;
+    A.base = (char *)pool_get(ar.off);
+    layout(A, rows, G, c, lam, z, u, its, kkt, flag, tr, ev, GT, CT, GE, CE, sE, admm_w, est_w);
+
+    Timer tm(s, timing);
+    tm.mark();
+    UOI_HIP(hipMemcpyAsync(lam, o->lambdas, sizeof(double) * q, hipMemcpyHostToDevice, s));
+    // model selection: bootstrap rows, Gram, ADMM sweep, supports
+    launch_boot_rows(s, o->seed, TAG_LASSO_BOOT, B1, n, rows);
+    launch_gram_f64(s, B1, n, rows, nullptr, p, X, p, 1, y, 1, G, c);
+    tm.mark();
+    P.G = G;
+    P.C = c;
+    P.lam = lam;
+    AdmmOut out{z, u, diag && diag->iters ? diag->iters : its, diag && diag->kkt ? diag->kkt : kkt, 0, 0};
+    admm_solve(s, P, o->precision, o->solver, admm_w, false, out, timing ? sm + 1 : nullptr);
+    tm.mark();
+    launch_support_and(s, B1, p, R, z, supp_out);
+    tm.mark();
+    // model estimation: splits, training / evaluation statistics, refits, union
+    launch_split(s, o->seed, TAG_LASSO_SPLIT, B2, n, ntr, flag);
+    launch_compact_rows(s, B2, n, flag, ntr, tr, ev);
+    launch_gram_f64(s, B2, ntr, tr, nullptr, p, X, p, 1, y, 1, GT, CT);
+    launch_gram_f64(s, B2, nev, ev, nullptr, p, X, p, 1, y, 1, GE, CE);
+    launch_colsq(s, B2, nev, ev, nullptr, 1, y, 1, sE);
+    tm.mark();
+    E.GT = GT; E.CT = CT; E.GE = GE; E.CE = CE; E.sE = sE;
+    estimate(s, E, est_w, beta_out, jstar_out, diag ? diag->losses : nullptr, timing ? sm + 6 : nullptr);
+    tm.mark();
+    if (diag && diag->sel_beta) transpose(s, B1, p, R, z, diag->sel_beta, true);
+    UOI_HIP(hipStreamSynchronize(s));
+    if (timing) {
+        sm[0] = tm.between(0, 1);
+        sm[4] = tm.between(2, 3);
+        sm[5] = tm.between(3, 4);
+    }
+    if (diag) {
+        diag->n_solves = (int64_t)B1 * R;
+        diag->n_unconverged = out.unconverged;
+        diag->max_iters = out.max_iters;
+        std::memcpy(diag->stage_ms, sm, sizeof(sm));
+    }
+    return out.unconverged ? UOI_ENOCONV : UOI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// UoI_VAR (d = 1)
+// ---------------------------------------------------------------------------
+static int var_fit(int T, int p, int d, const double *series, int block_len, const uoi_opts *o,
+                   double *A_out, double *mu_out, uint64_t *supp_out, int32_t *jstar_out, uoi_diag *diag) {
+    check_opts(o, true);
+    UOI_REQUIRE(d == 1, "only VAR(1) is supported (d must be 1)");
+    UOI_REQUIRE(T >= 3 && p >= 1, "need T >= 3 and p >= 1");
+    UOI_REQUIRE(series && A_out && mu_out && supp_out && jstar_out, "NULL data or output pointer");
+    const int N = T - 1;
+    const int L = block_len > 0 ? block_len : var_block_len_default(N);
+    UOI_REQUIRE(L <= N, "block_len must be <= T-1");
+    const int nblk = (N + L - 1) / L;
+    const int nbt = split_count(nblk, o->train_num, o->train_den);
+    UOI_REQUIRE(nbt >= 1 && nbt < nblk, "estimation split leaves no training or evaluation block");
+    UOI_REQUIRE((int64_t)o->B1 * o->q * p <= (int64_t)1 << 30, "too many solves");
+    hipStream_t s = (hipStream_t)o->stream;
+    check_finite(s, series, (size_t)T * p, "series");
+    const bool timing = (o->flags & UOI_FLAG_TIMING) != 0;
+    float sm[8] = {0};
+
+    const int B1 = o->B1, B2 = o->B2, q = o->q, pe = p, R = q * p;
+    AdmmProblem P{B1, p, q, pe, R, nullptr, nullptr, nullptr, o->rho, o->kkt_tol, o->max_iter,
+                  o->check_every};
+    EstimProblem E{B2, p, pe, q, R, nullptr, nullptr, nullptr, nullptr, nullptr, supp_out};
+    size_t nst = (size_t)B1 * p * R;
+    auto layout = [&](Arena &a, int32_t *&rows, double *&G, double *&C, double *&lam, double *&z,
+                      double *&u, int32_t *&its, double *&kkt, uint8_t *&flag, int32_t *&tr,
+                      int32_t *&ev, int32_t *&ntr, int32_t *&nev, double *&GT, double *&CT,
+                      double *&GE, double *&CE, double *&sE, void *&admm_w, void *&est_w) {
+        rows = a.take<int32_t>((size_t)B1 * N);
+        G = a.take<double>((size_t)B1 * p * p);
+        C = a.take<double>((size_t)B1 * p * pe);
+        lam = a.take<double>(q);
+        z = a.take<double>(nst);
+        u = a.take<double>(nst);
+        its = a.take<int32_t>((size_t)B1 * R);
+        kkt = a.take<double>((size_t)B1 * R);
+        flag = a.take<uint8_t>((size_t)B2 * nblk);
+        tr = a.take<int32_t>((size_t)B2 * N);
+        ev = a.take<int32_t>((size_t)B2 * N);
+        ntr = a.take<int32_t>(B2);
+        nev = a.take<int32_t>(B2);
+        GT = a.take<double>((size_t)B2 * p * p);
+        CT = a.take<double>((size_t)B2 * p * pe);
+        GE = a.take<double>((size_t)B2 * p * p);
+        CE = a.take<double>((size_t)B2 * p * pe);
+        sE = a.take<double>((size_t)B2 * pe);
+        admm_w = a.take<char>(admm_work_bytes(P, o->precision, o->solver));
+        est_w = a.take<char>(estim_work_bytes(E));
+    };
+    int32_t *rows, *its, *tr, *ev, *ntr, *nev;
+    double *G, *C, *lam, *z, *u, *kkt, *GT, *CT, *GE, *CE, *sE;
+    uint8_t *flag;
+    void *admm_w, *est_w;
+    Arena ar;
+    layout(ar, rows, G, C, lam, z, u, its, kkt, flag, tr, ev, ntr, nev, GT, CT, GE, CE, sE, admm_w, est_w);
+    Arena A;
+    A.cap = ar.off;
+    A.base = (char *)pool_get(ar.off);
+    layout(A, rows, G, C, lam, z, u, its, kkt, flag, tr, ev, ntr, nev, GT, CT, GE, CE, sE, admm_w, est_w);
+
+    const double *Xd = series, *Yd = series + p;  // regression row r: x = series[r], y = series[r+1]
+    Timer tm(s, timing);
+    tm.mark();
+    UOI_HIP(hipMemcpyAsync(lam, o->lambdas, sizeof(double) * q, hipMemcpyHostToDevice, s));
+    launch_var_boot_rows(s, o->seed, B1, N, L, rows);
+    launch_gram_f64(s, B1, N, rows, nullptr, p, Xd, p, pe, Yd, p, G, C);
+    tm.mark();
+    P.G = G;
+    P.C = C;
+    P.lam = lam;
+    AdmmOut out{z, u, diag && diag->iters ? diag->iters : its, diag && diag->kkt ? diag->kkt : kkt, 0, 0};
+    admm_solve(s, P, o->precision, o->solver, admm_w, false, out, timing ? sm + 1 : nullptr);
+    tm.mark();
+    launch_support_and(s, B1, p, R, z, supp_out);
+    tm.mark();
+    launch_split(s, o->seed, TAG_VAR_SPLIT, B2, nblk, nbt, flag);
+    launch_expand_blocks(s, B2, nblk, N, L, flag, tr, ev, ntr, nev);
+    launch_gram_f64(s, B2, N, tr, ntr, p, Xd, p, pe, Yd, p, GT, CT);
+    launch_gram_f64(s, B2, N, ev, nev, p, Xd, p, pe, Yd, p, GE, CE);
+    launch_colsq(s, B2, N, ev, nev, pe, Yd, p, sE);
+    tm.mark();
+    E.GT = GT; E.CT = CT; E.GE = GE; E.CE = CE; E.sE = sE;
+    estimate(s, E, est_w, A_out, jstar_out, diag ? diag->losses : nullptr, timing ? sm + 6 : nullptr);
+    tm.mark();
+    UOI_HIP(hipMemsetAsync(mu_out, 0, sizeof(double) * p, s));
+    if (diag && diag->sel_beta) transpose(s, B1, p, R, z, diag->sel_beta, true);
+    UOI_HIP(hipStreamSynchronize(s));
+    if (timing) {
+        sm[0] = tm.between(0, 1);
+        sm[4] = tm.between(2, 3);
+        sm[5] = tm.between(3, 4);
+    }
+    if (diag) {
+        diag->n_solves = (int64_t)B1 * R;
+        diag->n_unconverged = out.unconverged;
+        diag->max_iters = out.max_iters;
+        std::memcpy(diag->stage_ms, sm, sizeof(sm));
+    }
+    return out.unconverged ? UOI_ENOCONV : UOI_OK;
+}
+
+// ---------------------------------------------------------------------------
+static int solve_batch(int nb, int p, const double *G, const double *c, const uoi_opts *o,
+                       const double *z0, const double *u0, double *z_out, double *u_out,
+                       int32_t *iters, double *kkt) {
+    check_opts(o, false);
+    UOI_REQUIRE(nb >= 1 && p >= 1, "need nb >= 1 and p >= 1");
+    UOI_REQUIRE(G && c && z_out, "NULL input or output pointer");
+    hipStream_t s = (hipStream_t)o->stream;
+    const int q = o->q, R = q;
+    AdmmProblem P{nb, p, q, 1, R, G, c, nullptr, o->rho, o->kkt_tol, o->max_iter, o->check_every};
+    size_t nst = (size_t)nb * p * R;
+    auto layout = [&](Arena &a, double *&lam, double *&z, double *&u, int32_t *&its, double *&kk,
+                      void *&w) {
+        lam = a.take<double>(q);
+        z = a.take<double>(nst);
+        u = a.take<double>(nst);
+        its = a.take<int32_t>((size_t)nb * R);
+        kk = a.take<double>((size_t)nb * R);
+        w = a.take<char>(admm_work_bytes(P, o->precision, o->solver));
+    };
+    double *lam, *z, *u, *kk;
+    int32_t *its;
+    void *w;
+    Arena ar;
+    layout(ar, lam, z, u, its, kk, w);
+    Arena A;
+    A.cap = ar.off;
+    A.base = (char *)pool_get(ar.off);
+    layout(A, lam, z, u, its, kk, w);
+    UOI_HIP(hipMemcpyAsync(lam, o->lambdas, sizeof(double) * q, hipMemcpyHostToDevice, s));
+    P.lam = lam;
+    bool warm = z0 != nullptr || u0 != nullptr;
+    if (warm) {
+        if (z0) transpose(s, nb, p, R, z0, z, false);
+        else UOI_HIP(hipMemsetAsync(z, 0, sizeof(double) * nst, s));
+        if (u0) transpose(s, nb, p, R, u0, u, false);
+        else UOI_HIP(hipMemsetAsync(u, 0, sizeof(double) * nst, s));
+    }
+    AdmmOut out{z, u, iters ? iters : its, kkt ? kkt : kk, 0, 0};
+    admm_solve(s, P, o->precision, o->solver, w, warm, out, nullptr);
+    transpose(s, nb, p, R, z, z_out, true);
+    if (u_out) transpose(s, nb, p, R, u, u_out, true);
+    UOI_HIP(hipStreamSynchronize(s));
+    return out.unconverged ? UOI_ENOCONV : UOI_OK;
+}
+
+template <class F>
+static int guarded(F &&f) {
+    try {
+        set_last_error("");
+        return f();
+    } catch (const Error &e) {
+        set_last_error(e.what());
+        return e.code;
+    } catch (const std::exception &e) {
+        set_last_error(e.what());
+        return UOI_EHIP;
+    } catch (...) {
+        set_last_error("unknown error");
+        return UOI_EHIP;
+    }
+}
+
+}  // namespace uoi
+
+using namespace uoi;
+
+extern "C" {
+
+void uoi_default_opts(uoi_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->rho = 1.0;
+    o->kkt_tol = 1e-6;
+    o->max_iter = 20000;
+    o->check_every = 10;
+    o->train_num = 4;
+    o->train_den = 5;
+    o->precision = UOI_FP64;
+    o->warm_start = UOI_COLD;
+    o->solver = UOI_SOLVER_BATCHED;
+}
+
+int uoi_lasso_fit(int32_t n, int32_t p, const double *X, const double *y, const uoi_opts *o,
+                  double *beta_out, uint64_t *supp_out, int32_t *jstar_out, uoi_diag *diag) {
+    return guarded([&] { return lasso_fit(n, p, X, y, o, beta_out, supp_out, jstar_out, diag); });
+}
+
+int uoi_var_fit(int32_t T, int32_t p, int32_t d, const double *series, int32_t block_len,
+                const uoi_opts *o, double *A_out, double *mu_out, uint64_t *supp_out,
+                int32_t *jstar_out, uoi_diag *diag) {
+    return guarded(
+        [&] { return var_fit(T, p, d, series, block_len, o, A_out, mu_out, supp_out, jstar_out, diag); });
+}
+
+int uoi_lasso_solve_batch(int32_t nb, int32_t p, const double *G, const double *c, const uoi_opts *o,
+                          const double *z0, const double *u0, double *z_out, double *u_out,
+                          int32_t *iters, double *kkt) {
+    return guarded([&] { return solve_batch(nb, p, G, c, o, z0, u0, z_out, u_out, iters, kkt); });
+}
+
+int uoi_gram(int32_t nb, int32_t m, const int32_t *rows, int32_t p, const double *X, int32_t ldx,
+             int32_t pe, const double *Y, int32_t ldy, double *G, double *C, void *stream) {
+    return guarded([&] {
+        UOI_REQUIRE(nb >= 1 && m >= 1 && p >= 1 && pe >= 0 && ldx >= p, "invalid Gram sizes");
+        UOI_REQUIRE(rows && X && G, "NULL pointer");
+        UOI_REQUIRE(pe == 0 || (Y && C && ldy >= pe), "pe > 0 needs Y, C and ldy >= pe");
+        launch_gram_f64((hipStream_t)stream, nb, m, rows, nullptr, p, X, ldx, pe, Y, ldy, G,
+                        pe ? C : nullptr);
+        UOI_HIP(hipStreamSynchronize((hipStream_t)stream));
+        return UOI_OK;
+    });
+}
+
+int uoi_bootstrap_rows(uint64_t seed, int32_t nb, int32_t n, int32_t *rows, void *stream) {
+    return guarded([&] {
+        UOI_REQUIRE(nb >= 1 && n >= 1 && rows, "invalid arguments");
+        launch_boot_rows((hipStream_t)stream, seed, TAG_LASSO_BOOT, nb, n, rows);
+        UOI_HIP(hipStreamSynchronize((hipStream_t)stream));
+        return UOI_OK;
+    });
+}
+
+int uoi_split_rows(uint64_t seed, int32_t nb, int32_t n, int32_t num, int32_t den, int32_t *train,
+                   int32_t *eval, void *stream) {
+    return guarded([&] {
+        UOI_REQUIRE(nb >= 1 && n >= 1 && den > 0 && num > 0 && num < den && train && eval,
+                    "invalid arguments");
+        int ntr = split_count(n, num, den);
+        UOI_REQUIRE(ntr >= 1 && ntr < n, "split leaves an empty side");
+        hipStream_t s = (hipStream_t)stream;
+        uint8_t *flag = (uint8_t *)pool_get((size_t)nb * n);
+        launch_split(s, seed, TAG_LASSO_SPLIT, nb, n, ntr, flag);
+        launch_compact_rows(s, nb, n, flag, ntr, train, eval);
+        UOI_HIP(hipStreamSynchronize(s));
+        return UOI_OK;
+    });
+}
+
+int uoi_var_boot_rows(uint64_t seed, int32_t nb, int32_t N, int32_t L, int32_t *rows, void *stream) {
+    return guarded([&] {
+        UOI_REQUIRE(nb >= 1 && N >= 1 && L >= 1 && L <= N && rows, "invalid arguments");
+        launch_var_boot_rows((hipStream_t)stream, seed, nb, N, L, rows);
+        UOI_HIP(hipStreamSynchronize((hipStream_t)stream));
+        return UOI_OK;
+    });
+}
+
+int uoi_var_split_rows(uint64_t seed, int32_t nb, int32_t N, int32_t L, int32_t num, int32_t den,
+                       int32_t *train, int32_t *eval, int32_t *ntr_out, int32_t *nev_out, void *stream) {
+    return guarded([&] {
+        UOI_REQUIRE(nb >= 1 && N >= 1 && L >= 1 && L <= N && den > 0 && num > 0 && num < den,
+                    "invalid arguments");
+        UOI_REQUIRE(train && eval && ntr_out && nev_out, "NULL pointer");
+        int nblk = (N + L - 1) / L, nbt = split_count(nblk, num, den);
+        UOI_REQUIRE(nbt >= 1 && nbt < nblk, "split leaves an empty side");
+        hipStream_t s = (hipStream_t)stream;
+        char *w = (char *)pool_get((size_t)nb * nblk + 2 * 256 * (size_t)nb + 1024);
+        uint8_t *flag = (uint8_t *)w;
+        int32_t *cnts = (int32_t *)(w + (((size_t)nb * nblk + 255) & ~size_t(255)));
+        launch_split(s, seed, TAG_VAR_SPLIT, nb, nblk, nbt, flag);
+        launch_expand_blocks(s, nb, nblk, N, L, flag, train, eval, cnts, cnts + nb);
+        UOI_HIP(hipMemcpyAsync(ntr_out, cnts, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, s));
+        UOI_HIP(hipMemcpyAsync(nev_out, cnts + nb, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, s));
+        UOI_HIP(hipStreamSynchronize(s));
+        return UOI_OK;
+    });
+}
+
+int uoi_spd_inverse(int32_t nb, int32_t p, const double *G, double rho, double *M, void *stream) {
+    return guarded([&] {
+        UOI_REQUIRE(nb >= 1 && p >= 1 && G && M && rho >= 0.0, "invalid arguments");
+        hipStream_t s = (hipStream_t)stream;
+        size_t wd = spd_inverse_work_doubles(nb, p);
+        double *w = wd ? (double *)pool_get(wd * sizeof(double)) : nullptr;
+        spd_inverse_f64(s, nb, p, G, rho, M, w);
+        UOI_HIP(hipStreamSynchronize(s));
+        return UOI_OK;
+    });
+}
+
+void uoi_release_workspace(void) {
+    try {
+        pool_release();
+    } catch (...) {
+    }
+}
+
+const char *uoi_last_error(void) { return g_last_error.c_str(); }
+
+const char *uoi_version(void) { return "uoi-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,609 @@
+// Batched LASSO-ADMM (Eq. (ADMM), Sec. II-E, in the scaled form of Boyd et al.
+// 2011, Sec. 6.4) for every (bootstrap, lambda[, equation]) solve of the model
+// selection step of Alg. 1 / Alg. 2.
+//
+// With M = (G + rho I)^{-1} and h = M c cached per bootstrap, one iteration is
+//     x = h + rho * M (z - u)          (x-minimisation)
+//     z = S_{lambda/rho}(x + u)        (z-minimisation: soft threshold)
+//     u = u + x - z                    (dual update)
+// All solves of one bootstrap share M, so the x-update of all of them is one
+// matrix product M [v_1 .. v_R] (v = z - u): the batched solver runs it on
+// MFMA with the threshold and dual update fused into its epilogue.  State is
+// feature-major ([bootstrap][feature][solve]) so that a K-step of the product
+// reads 16 consecutive solves of one feature row.
+//
+// Convergence is the relative KKT residual of the LASSO (evaluated in float64
+// with the float64 Gram) every `check_every` iterations; a solve that meets the
+// tolerance is frozen (its z is the verified iterate) and a tile whose solves
+// are all frozen skips its work.
+#include <algorithm>
+#include <cstring>
+
+#include "common.hpp"
+
+namespace uoi {
+
+// ---------------------------------------------------------------------------
+// Batched product Y_b = A_b V_b, A_b symmetric p x p, V_b p x R (row-major).
+// Workgroup = 4 waves stacked along rows; a wave owns a (16 FM) x (16 FN) block
+// of the output as FM x FN MFMA 16x16x4 accumulators.  Because A is symmetric,
+// the MFMA operand A[i][k] is read as A[k][i]: 16 consecutive doubles of a row.
+// ---------------------------------------------------------------------------
+template <typename T, int FM, int FN>
+struct Tile {
+    typedef typename std::conditional<std::is_same<T, double>::value, dx4, fx4>::type acc_t;
+    acc_t acc[FM][FN];
+};
+
+template <typename T, int FM, int FN, class Epi>
+__global__ __launch_bounds__(256) void k_bgemm(int p, int R, const T *__restrict__ A,
+                                               const T *__restrict__ V, Epi epi) {
+    typedef typename Tile<T, FM, FN>::acc_t acc_t;
+    const int b = blockIdx.z;
+    const int r0 = blockIdx.x * (16 * FN);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int i_base = blockIdx.y * (64 * FM) + wid * (16 * FM);
+    const int lr = lane & 15, lk = lane >> 4;
+    if (!epi.tile_active(b, r0, 16 * FN)) return;
+    if (i_base >= p) return;  // whole wave below the matrix (no shared memory used)
+
+    const T *Ab = A + (size_t)b * p * p;
+    const T *Vb = V + (size_t)b * p * R;
+    acc_t acc[FM][FN];
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int c = 0; c < FN; ++c)
+            for (int t = 0; t < 4; ++t) acc[a][c][t] = 0;
+
+    int icol[FM], rcol[FN];
+    bool iok[FM], rok[FN];
+#pragma unroll
+    for (int a = 0; a < FM; ++a) {
+        icol[a] = i_base + 16 * a + lr;
+        iok[a] = icol[a] < p;
+    }
+#pragma unroll
+    for (int c = 0; c < FN; ++c) {
+        rcol[c] = r0 + 16 * c + lr;
+        rok[c] = rcol[c] < R;
+    }
+
+    const int pk = p & ~15;  // main loop: 16 rows of k per trip, 4 MFMA K-steps
+    for (int k0 = 0; k0 < pk; k0 += 16) {
+        T av[4][FM], bv[4][FN];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int k = k0 + 4 * s + lk;
+#pragma unroll
+            for (int a = 0; a < FM; ++a) av[s][a] = iok[a] ? Ab[(size_t)k * p + icol[a]] : T(0);
+#pragma unroll
+            for (int c = 0; c < FN; ++c) bv[s][c] = rok[c] ? Vb[(size_t)k * R + rcol[c]] : T(0);
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int a = 0; a < FM; ++a)
+#pragma unroll
+                for (int c = 0; c < FN; ++c) acc[a][c] = mfma16x16x4(av[s][a], bv[s][c], acc[a][c]);
+    }
+    for (int k0 = pk; k0 < p; k0 += 4) {  // ragged tail
+        const int k = k0 + lk;
+        const bool kok = k < p;
+#pragma unroll
+        for (int a = 0; a < FM; ++a) {
+            T av = (kok && iok[a]) ? Ab[(size_t)k * p + icol[a]] : T(0);
+#pragma unroll
+            for (int c = 0; c < FN; ++c) {
+                T bv = (kok && rok[c]) ? Vb[(size_t)k * R + rcol[c]] : T(0);
+                acc[a][c] = mfma16x16x4(av, bv, acc[a][c]);
+            }
+        }
+    }
+    // element (i, r) of the block: i = i_base + 16a + mfma_row(lk, t), r = r0 + 16c + lr
+    epi.apply(b, i_base, r0, lr, lk, acc);
+}
+
+// --- epilogue: plain store --------------------------------------------------
+template <typename T, int FM, int FN>
+struct StoreEpi {
+    T *Y;
+    int p, R;
+    __device__ bool tile_active(int, int, int) const { return true; }
+    template <class Acc>
+    __device__ void apply(int b, int i_base, int r0, int lr, int lk, Acc (&acc)[FM][FN]) const {
+#pragma unroll
+        for (int a = 0; a < FM; ++a)
+#pragma unroll
+            for (int c = 0; c < FN; ++c)
+                for (int t = 0; t < 4; ++t) {
+                    int i = i_base + 16 * a + mfma_row(T(0), lk, t), r = r0 + 16 * c + lr;
+                    if (i < p && r < R) Y[((size_t)b * p + i) * R + r] = (T)acc[a][c][t];
+                }
+    }
+};
+
+// --- epilogue: ADMM iteration ----------------------------------------------
+// x = h + rho*acc (acc = M v), z = S(x + u, lam/rho), u += x - z, v' = z - u.
+template <typename T, int FM, int FN>
+struct AdmmEpi {
+    const T *h;          // [nb][p][pe]
+    T *z, *u, *vout;     // [nb][p][R]
+    const uint8_t *state;// [nb][R] 0 = active
+    const double *lam;   // [q]
+    int p, R, pe;
+    T rho, inv_rho;
+    __device__ bool tile_active(int b, int r0, int w) const {
+        int hi = min(R, r0 + w);
+        for (int r = r0; r < hi; ++r)
+            if (state[(size_t)b * R + r] == 0) return true;
+        return false;
+    }
+    template <class Acc>
+    __device__ void apply(int b, int i_base, int r0, int lr, int lk, Acc (&acc)[FM][FN]) const {
+#pragma unroll
+        for (int c = 0; c < FN; ++c) {
+            int r = r0 + 16 * c + lr;
+            if (r >= R || state[(size_t)b * R + r] != 0) continue;
+            int e = r % pe;
+            T thr = (T)lam[r / pe] * inv_rho;
+#pragma unroll
+            for (int a = 0; a < FM; ++a)
+                for (int t = 0; t < 4; ++t) {
+                    int i = i_base + 16 * a + mfma_row(T(0), lk, t);
+                    if (i >= p) continue;
+                    size_t o = ((size_t)b * p + i) * R + r;
+                    T x = h[((size_t)b * p + i) * pe + e] + rho * (T)acc[a][c][t];
+                    T uo = u[o];
+                    T zn = soft_threshold(x + uo, thr);
+                    T un = uo + x - zn;
+                    z[o] = zn;
+                    u[o] = un;
+                    vout[o] = zn - un;
+                }
+        }
+    }
+};
+
+// --- epilogue: KKT residual --------------------------------------------------
+// acc = (G z)_i; g = c_i - acc; v_i as in the KKT definition; per-solve max over
+// i is reduced in the wave and then with an atomic max on the bit pattern.
+template <typename T, int FM, int FN>
+struct KktEpi {
+    const double *C;     // [nb][p][pe]
+    const T *z;          // [nb][p][R]
+    const uint8_t *state;
+    const double *lam;
+    double *vmax;        // [nb][R]  (zeroed before the launch)
+    int p, R, pe;
+    bool only_active;
+    __device__ bool tile_active(int b, int r0, int w) const {
+        if (!only_active) return true;
+        int hi = min(R, r0 + w);
+        for (int r = r0; r < hi; ++r)
+            if (state[(size_t)b * R + r] == 0) return true;
+        return false;
+    }
+    template <class Acc>
+    __device__ void apply(int b, int i_base, int r0, int lr, int lk, Acc (&acc)[FM][FN]) const {
+#pragma unroll
+        for (int c = 0; c < FN; ++c) {
+            int r = r0 + 16 * c + lr;
+            bool rok = r < R && !(only_active && state[(size_t)b * R + r] != 0);
+            int e = rok ? r % pe : 0;
+            double lm = rok ? lam[r / pe] : 0.0;
+            double m = 0.0;
+#pragma unroll
+            for (int a = 0; a < FM; ++a)
+                for (int t = 0; t < 4; ++t) {
+                    int i = i_base + 16 * a + mfma_row(T(0), lk, t);
+                    if (!rok || i >= p) continue;
+                    size_t o = ((size_t)b * p + i) * R + r;
+                    double g = C[((size_t)b * p + i) * pe + e] - (double)acc[a][c][t];
+                    double zi = (double)z[o];
+                    double v = zi != 0.0 ? fabs(g - (zi > 0 ? lm : -lm)) : fmax(0.0, fabs(g) - lm);
+                    m = fmax(m, v);
+                }
+            // lanes lr, lr+16, lr+32, lr+48 hold the same solve
+            m = fmax(m, __shfl_xor(m, 16));
+            m = fmax(m, __shfl_xor(m, 32));
+            if (rok && lk == 0 && m > 0.0) atomic_max_nonneg(&vmax[(size_t)b * R + r], m);
+        }
+    }
+};
+
+// For the float64 path the Gram product reads z directly; a float32 z is fed to
+// the float64 product through this converted copy.
+__global__ void k_f32_to_f64(size_t n, const float *__restrict__ a, double *__restrict__ b) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (double)a[i];
+}
+__global__ void k_f64_to_f32(size_t n, const double *__restrict__ a, float *__restrict__ b) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (float)a[i];
+}
+
+// per-(b, e) ||c||_inf
+__global__ void k_cnorm(int p, int pe, const double *__restrict__ C, double *__restrict__ cn) {
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    int b = blockIdx.y;
+    if (e >= pe) return;
+    double m = 0.0;
+    for (int i = 0; i < p; ++i) m = fmax(m, fabs(C[((size_t)b * p + i) * pe + e]));
+    cn[(size_t)b * pe + e] = m;
+}
+
+// After a KKT evaluation: freeze solves that meet the tolerance.
+// state: 0 active, 1 converged, 2 parked (met park_tol, waits for float64).
+__global__ void k_freeze(int nb, int R, int pe, const double *__restrict__ vmax,
+                         const double *__restrict__ cn, double tol, double park_tol, int it,
+                         uint8_t *__restrict__ state, int32_t *__restrict__ iters,
+                         double *__restrict__ kkt, int *__restrict__ active) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    bool act = false;
+    if (s < nb * R) {
+        int b = s / R, r = s % R;
+        if (state[s] == 0) {
+            double c = cn[(size_t)b * pe + r % pe];
+            double rel = c > 0.0 ? vmax[s] / c : vmax[s];
+            kkt[s] = rel;
+            if (rel <= tol) {
+                state[s] = 1;
+                iters[s] = it;
+            } else if (rel <= park_tol) {
+                state[s] = 2;
+            } else {
+                act = true;
+            }
+        }
+    }
+    unsigned long long bal = __ballot(act);
+    if ((threadIdx.x & 63) == 0 && bal) atomicAdd(active, __popcll(bal));
+}
+
+template <typename T>
+__global__ void k_init_state(size_t n, const T *__restrict__ z0, const T *__restrict__ u0,
+                             T *__restrict__ z, T *__restrict__ u, T *__restrict__ v) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        T a = z0 ? z0[i] : T(0), c = u0 ? u0[i] : T(0);
+        z[i] = a;
+        u[i] = c;
+        v[i] = a - c;
+    }
+}
+
+// v = z - u after a precision change or a restart
+template <typename T>
+__global__ void k_refresh_v(size_t n, const T *__restrict__ z, const T *__restrict__ u,
+                            T *__restrict__ v0, T *__restrict__ v1) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        T d = z[i] - u[i];
+        v0[i] = d;
+        v1[i] = d;
+    }
+}
+
+__global__ void k_unpark(size_t n, uint8_t *__restrict__ state) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && state[i] == 2) state[i] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Plain solver: one workgroup runs one whole solve with matrix-vector products
+// (the per-solve organisation of the paper's distributed ADMM, here without
+// row sharding).  z, u, v live in LDS; M and G are streamed every iteration.
+// ---------------------------------------------------------------------------
+constexpr int PLAIN_MAX_ROWS = 16;  // p <= 256 * 16
+
+__global__ __launch_bounds__(256) void k_admm_plain(int p, int pe, int R, const double *__restrict__ M,
+                                                    const double *__restrict__ h,
+                                                    const double *__restrict__ G,
+                                                    const double *__restrict__ C,
+                                                    const double *__restrict__ lam,
+                                                    const double *__restrict__ cn, double rho,
+                                                    double tol, int max_iter, int check_every,
+                                                    double *__restrict__ zout,
+                                                    double *__restrict__ uout,
+                                                    int32_t *__restrict__ iters,
+                                                    double *__restrict__ kkt) {
+    extern __shared__ double sm[];
+    double *v = sm, *z = sm + p, *u = sm + 2 * p;
+    __shared__ double red[4];
+    __shared__ int done_s;
+    const int s = blockIdx.x;
+    const int b = s / R, r = s % R, e = r % pe;
+    const double lm = lam[r / pe], thr = lm / rho;
+    const double cnorm = cn[(size_t)b * pe + e];
+    const double *Mb = M + (size_t)b * p * p;
+    const double *Gb = G + (size_t)b * p * p;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < p; i += 256) {
+        z[i] = zout[((size_t)b * p + i) * R + r];
+        u[i] = uout[((size_t)b * p + i) * R + r];
+        v[i] = z[i] - u[i];
+    }
+    __syncthreads();
+    int it = 0, status = -1;
+    double rel = 0.0;
+    for (;;) {
+        if (it % check_every == 0 || it == max_iter) {
+            // KKT: g = c - G z
+            double m = 0.0;
+            for (int i = tid; i < p; i += 256) {
+                double acc = 0.0;
+                for (int k = 0; k < p; ++k) acc += Gb[(size_t)k * p + i] * z[k];
+                double g = C[((size_t)b * p + i) * pe + e] - acc;
+                double zi = z[i];
+                double vv = zi != 0.0 ? fabs(g - (zi > 0 ? lm : -lm)) : fmax(0.0, fabs(g) - lm);
+                m = fmax(m, vv);
+            }
+            m = wave_max(m);
+            if ((tid & 63) == 0) red[tid >> 6] = m;
+            __syncthreads();
+            if (tid == 0) {
+                double mm = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+                rel = cnorm > 0.0 ? mm / cnorm : mm;
+                red[0] = rel;
+                done_s = (rel <= tol) ? 1 : (it >= max_iter ? 2 : 0);
+            }
+            __syncthreads();
+            rel = red[0];
+            if (done_s) {
+                status = done_s == 1 ? it : -1;
+                break;
+            }
+            __syncthreads();
+        }
+        // x = h + rho M v for my rows, then the threshold and dual update
+        double xr[PLAIN_MAX_ROWS];
+        int nr = 0;
+        for (int i = tid; i < p; i += 256, ++nr) {
+            double acc = 0.0;
+            for (int k = 0; k < p; ++k) acc += Mb[(size_t)k * p + i] * v[k];
+            xr[nr] = h[((size_t)b * p + i) * pe + e] + rho * acc;
+        }
+        __syncthreads();
+        nr = 0;
+        for (int i = tid; i < p; i += 256, ++nr) {
+            double zn = soft_threshold(xr[nr] + u[i], thr);
+            double un = u[i] + xr[nr] - zn;
+            z[i] = zn;
+            u[i] = un;
+            v[i] = zn - un;
+        }
+        __syncthreads();
+        ++it;
+    }
+    for (int i = tid; i < p; i += 256) {
+        zout[((size_t)b * p + i) * R + r] = z[i];
+        uout[((size_t)b * p + i) * R + r] = u[i];
+    }
+    if (tid == 0) {
+        iters[s] = status;
+        kkt[s] = rel;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+template <typename T, int FM, int FN, class Epi>
+static void run_bgemm(hipStream_t s, int nb, int p, int R, const T *A, const T *V, const Epi &epi) {
+    dim3 grid(cdiv(R, 16 * FN), cdiv(p, 64 * FM), nb);
+    hipLaunchKernelGGL((k_bgemm<T, FM, FN, Epi>), grid, dim3(256), 0, s, p, R, A, V, epi);
+    UOI_LAUNCH_CHECK();
+}
+
+// Column-block width: the smallest 16-multiple that covers R up to 64.
+#define UOI_DISPATCH_FN(R, ...)                                   \
+    do {                                                          \
+        if ((R) <= 16) { constexpr int FN = 1; __VA_ARGS__; }      \
+        else if ((R) <= 32) { constexpr int FN = 2; __VA_ARGS__; } \
+        else if ((R) <= 48) { constexpr int FN = 3; __VA_ARGS__; } \
+        else { constexpr int FN = 4; __VA_ARGS__; }                \
+    } while (0)
+
+void launch_matmul_f64(hipStream_t s, int nb, int p, int R, const double *A, const double *V,
+                       double *Y) {
+    UOI_DISPATCH_FN(R, {
+        StoreEpi<double, 1, FN> epi{Y, p, R};
+        run_bgemm<double, 1, FN>(s, nb, p, R, A, V, epi);
+    });
+}
+
+void launch_cnorm(hipStream_t s, int nb, int p, int pe, const double *C, double *cn) {
+    hipLaunchKernelGGL(k_cnorm, dim3(cdiv(pe, 64), nb), dim3(64), 0, s, p, pe, C, cn);
+    UOI_LAUNCH_CHECK();
+}
+
+namespace {
+struct AdmmWork {
+    double *M, *h, *cn, *vmax;
+    uint8_t *state;
+    int *active;
+    // float64 iteration buffers
+    double *v0, *v1;
+    // float32 phase
+    float *M32, *h32, *z32, *u32, *w0, *w1;
+    double *z64tmp;
+};
+
+AdmmWork carve(const AdmmProblem &P, int precision, int solver, Arena &ar) {
+    AdmmWork w{};
+    size_t np2 = (size_t)P.nb * P.p * P.p, nst = (size_t)P.nb * P.p * P.R;
+    w.M = ar.take<double>(np2);
+    w.h = ar.take<double>((size_t)P.nb * P.p * P.pe);
+    w.cn = ar.take<double>((size_t)P.nb * P.pe);
+    w.vmax = ar.take<double>((size_t)P.nb * P.R);
+    w.state = ar.take<uint8_t>((size_t)P.nb * P.R);
+    w.active = ar.take<int>(1);
+    if (solver == UOI_SOLVER_BATCHED) {
+        w.v0 = ar.take<double>(nst);
+        w.v1 = ar.take<double>(nst);
+        if (precision == UOI_MIXED) {
+            w.M32 = ar.take<float>(np2);
+            w.h32 = ar.take<float>((size_t)P.nb * P.p * P.pe);
+            w.z32 = ar.take<float>(nst);
+            w.u32 = ar.take<float>(nst);
+            w.w0 = ar.take<float>(nst);
+            w.w1 = ar.take<float>(nst);
+        }
+    }
+    return w;
+}
+}  // namespace
+
+size_t admm_work_bytes(const AdmmProblem &P, int precision, int solver) {
+    Arena ar;
+    carve(P, precision, solver, ar);
+    return ar.off + spd_inverse_work_doubles(P.nb, P.p) * sizeof(double) + 4096;
+}
+
+// KKT evaluation of (a subset of) solves followed by the freeze step; returns the
+// number of solves still active.
+template <typename T>
+static int check(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T *z, bool only_active,
+                 double park_tol, int it, AdmmOut &out) {
+    UOI_HIP(hipMemsetAsync(w.vmax, 0, sizeof(double) * (size_t)P.nb * P.R, s));
+    UOI_HIP(hipMemsetAsync(w.active, 0, sizeof(int), s));
+    if (std::is_same<T, double>::value) {
+        UOI_DISPATCH_FN(P.R, {
+            KktEpi<double, 1, FN> epi{P.C, (const double *)z, w.state, P.lam, w.vmax, P.p, P.R, P.pe,
+                                      only_active};
+            run_bgemm<double, 1, FN>(s, P.nb, P.p, P.R, P.G, (const double *)z, epi);
+        });
+    } else {
+        // float32 z: widen to float64 first so the product is the float64 Gram times z
+        size_t n = (size_t)P.nb * P.p * P.R;
+        hipLaunchKernelGGL(k_f32_to_f64, dim3(cdiv(n, 256)), dim3(256), 0, s, n, (const float *)z,
+                           w.v0);
+        UOI_LAUNCH_CHECK();
+        UOI_DISPATCH_FN(P.R, {
+            KktEpi<double, 1, FN> epi{P.C, w.v0, w.state, P.lam, w.vmax, P.p, P.R, P.pe, only_active};
+            run_bgemm<double, 1, FN>(s, P.nb, P.p, P.R, P.G, w.v0, epi);
+        });
+    }
+    int ns = P.nb * P.R;
+    hipLaunchKernelGGL(k_freeze, dim3(cdiv(ns, 256)), dim3(256), 0, s, P.nb, P.R, P.pe, w.vmax, w.cn,
+                       P.tol, park_tol, it, w.state, out.iters, out.kkt, w.active);
+    UOI_LAUNCH_CHECK();
+    int active = 0;
+    UOI_HIP(hipMemcpyAsync(&active, w.active, sizeof(int), hipMemcpyDeviceToHost, s));
+    UOI_HIP(hipStreamSynchronize(s));
+    return active;
+}
+
+template <typename T>
+static int sweep(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T *M, const T *h,
+                 T *z, T *u, T *va, T *vb, int &it, int it_cap, double park_tol, AdmmOut &out) {
+    int active = check<T>(s, P, w, z, true, park_tol, it, out);
+    while (active > 0 && it < it_cap) {
+        int n = std::min(P.check_every, it_cap - it);
+        for (int t = 0; t < n; ++t) {
+            T *vin = (it & 1) ? vb : va;
+            T *vout = (it & 1) ? va : vb;
+            UOI_DISPATCH_FN(P.R, {
+                AdmmEpi<T, 1, FN> epi{h, z, u, vout, w.state, P.lam, P.p, P.R, P.pe, (T)P.rho,
+                                      (T)(1.0 / P.rho)};
+                run_bgemm<T, 1, FN>(s, P.nb, P.p, P.R, M, vin, epi);
+            });
+            ++it;
+        }
+        active = check<T>(s, P, w, z, true, park_tol, it, out);
+    }
+    return active;
+}
+
+void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, void *work,
+                bool warm, AdmmOut &out, float *stage_ms) {
+    Arena ar;
+    ar.base = (char *)work;
+    ar.cap = (size_t)-1;
+    AdmmWork w = carve(P, precision, solver, ar);
+    double *spd_work = ar.take<double>(spd_inverse_work_doubles(P.nb, P.p));
+    const size_t nst = (size_t)P.nb * P.p * P.R;
+    const int ns = P.nb * P.R;
+
+    hipEvent_t ev[3];
+    if (stage_ms)
+        for (auto &e : ev) UOI_HIP(hipEventCreate(&e));
+    if (stage_ms) UOI_HIP(hipEventRecord(ev[0], s));
+
+    // factor: M = (G + rho I)^{-1}, h = M C, and ||c||_inf per equation
+    spd_inverse_f64(s, P.nb, P.p, P.G, P.rho, w.M, spd_work);
+    launch_matmul_f64(s, P.nb, P.p, P.pe, w.M, P.C, w.h);
+    launch_cnorm(s, P.nb, P.p, P.pe, P.C, w.cn);
+    if (stage_ms) UOI_HIP(hipEventRecord(ev[1], s));
+
+    UOI_HIP(hipMemsetAsync(w.state, 0, ns, s));
+    {
+        std::vector<int32_t> neg(ns, -1);
+        UOI_HIP(hipMemcpyAsync(out.iters, neg.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, s));
+        UOI_HIP(hipStreamSynchronize(s));
+    }
+    if (!warm) {
+        UOI_HIP(hipMemsetAsync(out.z, 0, sizeof(double) * nst, s));
+        UOI_HIP(hipMemsetAsync(out.u, 0, sizeof(double) * nst, s));
+    }
+    int it = 0, active = 0;
+    if (solver == UOI_SOLVER_PLAIN) {
+        size_t lds = sizeof(double) * 3 * (size_t)P.p;
+        UOI_REQUIRE(P.p <= 256 * PLAIN_MAX_ROWS && lds <= 160 * 1024, "plain solver: p too large");
+        hipLaunchKernelGGL(k_admm_plain, dim3(ns), dim3(256), lds, s, P.p, P.pe, P.R, w.M, w.h, P.G,
+                           P.C, P.lam, w.cn, P.rho, P.tol, P.max_iter, P.check_every, out.z, out.u,
+                           out.iters, out.kkt);
+        UOI_LAUNCH_CHECK();
+    } else if (precision == UOI_FP64) {
+        hipLaunchKernelGGL(k_refresh_v<double>, dim3(cdiv(nst, 256)), dim3(256), 0, s, nst, out.z,
+                           out.u, w.v0, w.v1);
+        UOI_LAUNCH_CHECK();
+        active = sweep<double>(s, P, w, w.M, w.h, out.z, out.u, w.v0, w.v1, it, P.max_iter, P.tol, out);
+    } else {
+        // float32 phase: operator and state in float32, KKT in float64; solves that
+        // reach 10x the tolerance are parked and finished in float64.
+        size_t np2 = (size_t)P.nb * P.p * P.p, nh = (size_t)P.nb * P.p * P.pe;
+        hipLaunchKernelGGL(k_f64_to_f32, dim3(cdiv(np2, 256)), dim3(256), 0, s, np2, w.M, w.M32);
+        hipLaunchKernelGGL(k_f64_to_f32, dim3(cdiv(nh, 256)), dim3(256), 0, s, nh, w.h, w.h32);
+        hipLaunchKernelGGL(k_f64_to_f32, dim3(cdiv(nst, 256)), dim3(256), 0, s, nst, out.z, w.z32);
+        hipLaunchKernelGGL(k_f64_to_f32, dim3(cdiv(nst, 256)), dim3(256), 0, s, nst, out.u, w.u32);
+        hipLaunchKernelGGL(k_refresh_v<float>, dim3(cdiv(nst, 256)), dim3(256), 0, s, nst, w.z32,
+                           w.u32, w.w0, w.w1);
+        UOI_LAUNCH_CHECK();
+        const double park = P.tol * 10.0;
+        active = sweep<float>(s, P, w, w.M32, w.h32, w.z32, w.u32, w.w0, w.w1, it, P.max_iter, park,
+                              out);
+        // widen the state and finish parked / active solves in float64
+        hipLaunchKernelGGL(k_f32_to_f64, dim3(cdiv(nst, 256)), dim3(256), 0, s, nst, w.z32, out.z);
+        hipLaunchKernelGGL(k_f32_to_f64, dim3(cdiv(nst, 256)), dim3(256), 0, s, nst, w.u32, out.u);
+        hipLaunchKernelGGL(k_unpark, dim3(cdiv(ns, 256)), dim3(256), 0, s, (size_t)ns, w.state);
+        hipLaunchKernelGGL(k_refresh_v<double>, dim3(cdiv(nst, 256)), dim3(256), 0, s, nst, out.z,
+                           out.u, w.v0, w.v1);
+        UOI_LAUNCH_CHECK();
+        int it64 = it;
+        active = sweep<double>(s, P, w, w.M, w.h, out.z, out.u, w.v0, w.v1, it64, P.max_iter + it,
+                               P.tol, out);
+        it = it64;
+    }
+    if (stage_ms) {
+        UOI_HIP(hipEventRecord(ev[2], s));
+        UOI_HIP(hipEventSynchronize(ev[2]));
+        UOI_HIP(hipEventElapsedTime(&stage_ms[0], ev[0], ev[1]));
+        UOI_HIP(hipEventElapsedTime(&stage_ms[1], ev[1], ev[2]));
+        for (auto &e : ev) UOI_HIP(hipEventDestroy(e));
+    }
+    UOI_HIP(hipStreamSynchronize(s));
+    // count unconverged solves and the largest iteration count
+    std::vector<int32_t> its(ns);
+    UOI_HIP(hipMemcpy(its.data(), out.iters, sizeof(int32_t) * ns, hipMemcpyDeviceToHost));
+    out.unconverged = 0;
+    out.max_iters = 0;
+    for (int v : its) {
+        if (v < 0) ++out.unconverged;
+        else out.max_iters = std::max(out.max_iters, v);
+    }
+    (void)active;
+}
+
+}  // namespace uoi

@@ -1,0 +1,220 @@
+// Shared host/device helpers of libuoi (gfx950 only).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/uoi.h"
+
+namespace uoi {
+
+// ---------------------------------------------------------------------------
+// Errors: internal code throws uoi::Error; the ABI layer converts it to a code.
+// ---------------------------------------------------------------------------
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define UOI_HIP(call)                                                                 \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            throw ::uoi::Error(e_ == hipErrorOutOfMemory ? UOI_ENOMEM : UOI_EHIP,     \
+                               std::string(#call) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+
+#define UOI_LAUNCH_CHECK() UOI_HIP(hipGetLastError())
+
+#define UOI_REQUIRE(cond, msg)                                  \
+    do {                                                        \
+        if (!(cond)) throw ::uoi::Error(UOI_EINVAL, (msg));     \
+    } while (0)
+
+void set_last_error(const std::string &m);
+
+// ---------------------------------------------------------------------------
+// Scratch pool: one grow-only device allocation per device, carved by Arena.
+// ---------------------------------------------------------------------------
+void *pool_get(size_t bytes);  // returns a device buffer of at least `bytes`
+void pool_release();
+
+struct Arena {
+    char *base = nullptr;
+    size_t off = 0, cap = 0;
+    template <class T>
+    T *take(size_t count) {
+        size_t bytes = (count * sizeof(T) + 255) & ~size_t(255);
+        if (base == nullptr) {  // sizing pass
+            off += bytes;
+            return nullptr;
+        }
+        if (off + bytes > cap) throw Error(UOI_ENOMEM, "scratch arena overflow");
+        T *p = reinterpret_cast<T *>(base + off);
+        off += bytes;
+        return p;
+    }
+};
+
+inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
+
+// ---------------------------------------------------------------------------
+// Device helpers.
+// ---------------------------------------------------------------------------
+typedef double dx4 __attribute__((ext_vector_type(4)));
+typedef float fx4 __attribute__((ext_vector_type(4)));
+
+// D(16x16) += A(16x4) * B(4x16).  In both precisions lane l supplies A[l%16][l/16]
+// and B[l/16][l%16].  The result layouts differ (measured on gfx950): in float64
+// lane l holds D[l/16 + 4t][l%16] in element t, in float32 D[4*(l/16) + t][l%16].
+__device__ __forceinline__ dx4 mfma16x16x4(double a, double b, dx4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ fx4 mfma16x16x4(float a, float b, fx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+// Row (within the 16x16 block) of element t of lane group lk = l/16.
+__device__ __forceinline__ int mfma_row(double, int lk, int t) { return lk + 4 * t; }
+__device__ __forceinline__ int mfma_row(float, int lk, int t) { return 4 * lk + t; }
+
+__device__ __forceinline__ double soft_threshold(double a, double t) {
+    return a > t ? a - t : (a < -t ? a + t : 0.0);
+}
+__device__ __forceinline__ float soft_threshold(float a, float t) {
+    return a > t ? a - t : (a < -t ? a + t : 0.0f);
+}
+
+// Max of non-negative doubles through their bit patterns (monotone for x >= 0).
+__device__ __forceinline__ void atomic_max_nonneg(double *addr, double v) {
+    atomicMax(reinterpret_cast<unsigned long long *>(addr),
+              (unsigned long long)__double_as_longlong(v));
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Counter-based index streams (SplitMix64 output function, Lemire range map).
+// ---------------------------------------------------------------------------
+enum : uint32_t { TAG_LASSO_BOOT = 1, TAG_LASSO_SPLIT = 2, TAG_VAR_BOOT = 3, TAG_VAR_SPLIT = 4 };
+
+__host__ __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+__host__ __device__ __forceinline__ uint64_t stream_key(uint64_t seed, uint32_t tag, uint32_t k,
+                                                        uint32_t i) {
+    return splitmix64(splitmix64(seed ^ ((uint64_t)tag << 56)) ^ (((uint64_t)k << 32) | i));
+}
+__host__ __device__ __forceinline__ uint32_t range_map(uint64_t r, uint32_t m) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return (uint32_t)__umul64hi(r, (uint64_t)m);
+#else
+    return (uint32_t)(((unsigned __int128)r * m) >> 64);
+#endif
+}
+
+inline int split_count(int n, int num, int den) { return (int)(((int64_t)n * num) / den); }
+inline int var_block_len_default(int N) {
+    int L = 1;
+    while ((int64_t)L * L * L < (int64_t)N) ++L;
+    return L;
+}
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (defined in the .hip files).
+// ---------------------------------------------------------------------------
+// index streams
+void launch_boot_rows(hipStream_t s, uint64_t seed, uint32_t tag_k0, int nb, int n, int32_t *rows);
+void launch_var_boot_rows(hipStream_t s, uint64_t seed, int nb, int N, int L, int32_t *rows);
+void launch_split(hipStream_t s, uint64_t seed, uint32_t tag, int nb, int cnt, int ntrain,
+                  uint8_t *is_train);
+void launch_compact_rows(hipStream_t s, int nb, int cnt, const uint8_t *is_train, int ntrain,
+                         int32_t *train, int32_t *eval);
+void launch_expand_blocks(hipStream_t s, int nb, int nblk, int N, int L, const uint8_t *is_train,
+                          int32_t *train, int32_t *eval, int32_t *ntr, int32_t *nev);
+
+// Gram: G[b] = X_r'X_r/m (full symmetric storage), C[b] = X_r'Y_r/m; per-batch row
+// counts may be given (mcount != nullptr) with row lists at stride m.
+void launch_gram_f64(hipStream_t s, int nb, int m, const int32_t *rows, const int32_t *mcount,
+                     int p, const double *X, int ldx, int pe, const double *Y, int ldy,
+                     double *G, double *C);
+// sum of squares of Y columns over sampled rows / m:  ss[b*pe + e]
+void launch_colsq(hipStream_t s, int nb, int m, const int32_t *rows, const int32_t *mcount,
+                  int pe, const double *Y, int ldy, double *ss);
+
+// Batched inverse of G + rho I by blocked Gauss-Jordan sweeps (writes M).
+void spd_inverse_f64(hipStream_t s, int nb, int p, const double *G, double rho, double *M,
+                     double *work);
+size_t spd_inverse_work_doubles(int nb, int p);
+
+// Batched products Y_b = A_b V_b with an epilogue (see gemm_epilogues in admm.hip).
+void launch_matmul_f64(hipStream_t s, int nb, int p, int R, const double *A, const double *V,
+                       double *Y);
+
+// ADMM state, batched FP64 / FP32 and plain.
+struct AdmmProblem {
+    int nb;              // bootstraps
+    int p;               // features
+    int q;               // lambdas
+    int pe;              // equations per bootstrap (1 for LASSO)
+    int R;               // q * pe solves per bootstrap
+    const double *G;     // [nb][p][p]
+    const double *C;     // [nb][p][pe]
+    const double *lam;   // device [q]
+    double rho;
+    double tol;
+    int max_iter;
+    int check_every;
+};
+
+struct AdmmOut {
+    double *z;           // [nb][p][R]   (feature-major state)
+    double *u;           // [nb][p][R]
+    int32_t *iters;      // [nb*R]
+    double *kkt;         // [nb*R]
+    int64_t unconverged;
+    int max_iters;
+};
+
+size_t admm_work_bytes(const AdmmProblem &P, int precision, int solver);
+void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, void *work,
+                bool warm, AdmmOut &out, float *stage_ms);
+
+// per-(b, e) ||c||_inf
+void launch_cnorm(hipStream_t s, int nb, int p, int pe, const double *C, double *cn);
+
+// supports: AND over bootstraps of (z != 0);  supp[r][W]
+void launch_support_and(hipStream_t s, int nb, int p, int R, const double *z, uint64_t *supp);
+
+// estimation
+struct EstimProblem {
+    int nb;                // B2
+    int p, pe, q, R;
+    const double *GT;      // [nb][p][p] training Grams
+    const double *CT;      // [nb][p][pe]
+    const double *GE;      // [nb][p][p] evaluation Grams
+    const double *CE;      // [nb][p][pe]
+    const double *sE;      // [nb][pe] mean squares of the responses on evaluation rows
+    const uint64_t *supp;  // [R][W]
+};
+size_t estim_work_bytes(const EstimProblem &E);
+void estimate(hipStream_t s, const EstimProblem &E, void *work, double *beta_out, int32_t *jstar,
+              double *losses_out, float *stage_ms);
+
+// finite check of an array; sets *flag (device int) to 1 on NaN/Inf
+void launch_finite_check(hipStream_t s, const double *x, size_t n, int *flag);
+
+}  // namespace uoi

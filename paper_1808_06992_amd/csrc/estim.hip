@@ -1,0 +1,509 @@
+// Model estimation of Alg. 1 / Alg. 2: for every estimation split k and every
+// support S_j (per equation e for VAR) the least-squares refit on the training
+// rows, its loss on the evaluation rows, the best support per split and the
+// average of the chosen refits (Eq. (union)).
+//
+// The paper runs OLS as ADMM with lambda = 0; here the same minimiser is
+// computed directly in float64 from the training normal equations
+// G_T[S,S] b = c_T[S]:
+//   - |S| <= kSmall: one workgroup per (split, support) gathers G_T[S,S] into
+//     LDS, factors it by Cholesky and solves (supports of uneven size run side by
+//     side, each workgroup sized by its own support);
+//   - larger supports: conjugate gradients on the masked operator, batched over
+//     all (split, support) pairs of a split so that every iteration is one MFMA
+//     product with G_T (the same kernel as the ADMM x-update).
+// The evaluation loss is the mean squared residual on the evaluation rows,
+// expanded through the evaluation Gram: L = s_E - 2 b'c_E + b'G_E b.
+#include <algorithm>
+#include <vector>
+
+#include "common.hpp"
+
+namespace uoi {
+
+namespace {
+constexpr int kSmall = 80;   // in-LDS Cholesky up to this support size
+constexpr double kCgTol = 1e-13;
+constexpr int kCgMaxIter = 4000;
+}
+
+__global__ void k_popcount(int R, int W, const uint64_t *__restrict__ supp, int32_t *__restrict__ cnt) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    int c = 0;
+    for (int w = 0; w < W; ++w) c += __popcll(supp[(size_t)r * W + w]);
+    cnt[r] = c;
+}
+
+// List the members of support r into idx (LDS); returns the size.
+__device__ int support_members(const uint64_t *__restrict__ sw, int W, int *idx) {
+    __shared__ int woff[1025];
+    // word offsets by a serial scan over at most W words (W <= 1024 checked on the host)
+    if (threadIdx.x == 0) {
+        int a = 0;
+        for (int w = 0; w < W; ++w) {
+            woff[w] = a;
+            a += __popcll(sw[w]);
+        }
+        woff[W] = a;
+    }
+    __syncthreads();
+    for (int w = threadIdx.x; w < W; w += blockDim.x) {
+        uint64_t x = sw[w];
+        int o = woff[w];
+        while (x) {
+            int bit = __ffsll((unsigned long long)x) - 1;
+            idx[o++] = w * 64 + bit;
+            x &= x - 1;
+        }
+    }
+    __syncthreads();
+    return woff[W];
+}
+
+// Loss on the evaluation rows through the evaluation Gram, for b on members idx.
+__device__ double eval_loss(int s, const int *idx, const double *bv, const double *GEb,
+                            const double *CEb, int p, int pe, int e, double sE) {
+    __shared__ double red[8];
+    double part = 0.0;
+    for (int t = threadIdx.x; t < s * s; t += blockDim.x) {
+        int a = t / s, c = t % s;
+        part += bv[a] * GEb[(size_t)idx[a] * p + idx[c]] * bv[c];
+    }
+    for (int a = threadIdx.x; a < s; a += blockDim.x) part -= 2.0 * bv[a] * CEb[(size_t)idx[a] * pe + e];
+    part = wave_sum(part);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
+    __syncthreads();
+    double tot = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += red[w];
+    __syncthreads();
+    return sE + tot;
+}
+
+// Small supports: gather, Cholesky, solve, loss.  Grid (R, nb); one workgroup per
+// (support r, split k); supports above kSmall are skipped here.
+__global__ __launch_bounds__(256) void k_ols_small(int p, int pe, int R, int W,
+                                                   const uint64_t *__restrict__ supp,
+                                                   const int32_t *__restrict__ cnt,
+                                                   const double *__restrict__ GT,
+                                                   const double *__restrict__ CT,
+                                                   const double *__restrict__ GE,
+                                                   const double *__restrict__ CE,
+                                                   const double *__restrict__ sE,
+                                                   double *__restrict__ Fit, double *__restrict__ loss,
+                                                   int *__restrict__ bad) {
+    extern __shared__ double Ls[];  // s x s
+    __shared__ int idx[kSmall];
+    __shared__ double bv[kSmall];
+    __shared__ int fail;
+    const int r = blockIdx.x, k = blockIdx.y;
+    if (cnt[r] > kSmall) return;
+    const int e = r % pe;
+    const double *GTb = GT + (size_t)k * p * p;
+    const double *CTb = CT + (size_t)k * p * pe;
+    const int s = support_members(supp + (size_t)r * W, W, idx);
+    if (threadIdx.x == 0) fail = 0;
+    for (int t = threadIdx.x; t < s * s; t += 256) {
+        int a = t / s, c = t % s;
+        Ls[t] = GTb[(size_t)idx[a] * p + idx[c]];
+    }
+    for (int a = threadIdx.x; a < s; a += 256) bv[a] = CTb[(size_t)idx[a] * pe + e];
+    __syncthreads();
+    // right-looking Cholesky, lower triangle
+    for (int j = 0; j < s; ++j) {
+        if (threadIdx.x == 0) {
+            double d = Ls[j * s + j];
+            if (!(d > 0.0)) { fail = 1; d = 1.0; }
+            Ls[j * s + j] = sqrt(d);
+        }
+        __syncthreads();
+        const double dj = Ls[j * s + j];
+        for (int i = j + 1 + threadIdx.x; i < s; i += 256) Ls[i * s + j] /= dj;
+        __syncthreads();
+        const int n = s - j - 1;
+        for (int t = threadIdx.x; t < n * n; t += 256) {
+            int i = j + 1 + t / n, c = j + 1 + t % n;
+            if (c <= i) Ls[i * s + c] -= Ls[i * s + j] * Ls[c * s + j];
+        }
+        __syncthreads();
+    }
+    // L y = c (column sweep), then L' b = y (row sweep)
+    for (int j = 0; j < s; ++j) {
+        if (threadIdx.x == 0) bv[j] /= Ls[j * s + j];
+        __syncthreads();
+        for (int i = j + 1 + threadIdx.x; i < s; i += 256) bv[i] -= Ls[i * s + j] * bv[j];
+        __syncthreads();
+    }
+    for (int j = s - 1; j >= 0; --j) {
+        if (threadIdx.x == 0) bv[j] /= Ls[j * s + j];
+        __syncthreads();
+        for (int i = threadIdx.x; i < j; i += 256) bv[i] -= Ls[j * s + i] * bv[j];
+        __syncthreads();
+    }
+    double *F = Fit + ((size_t)k * R + r) * p;
+    for (int i = threadIdx.x; i < p; i += 256) F[i] = 0.0;
+    __syncthreads();
+    for (int a = threadIdx.x; a < s; a += 256) F[idx[a]] = bv[a];
+    double L = eval_loss(s, idx, bv, GE + (size_t)k * p * p, CE + (size_t)k * p * pe, p, pe, e,
+                         sE[(size_t)k * pe + e]);
+    if (threadIdx.x == 0) {
+        loss[(size_t)k * R + r] = L;
+        if (fail) atomicOr(bad, 1);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Conjugate gradients for the large supports (columns c < nL of each split,
+// support Lidx[c]); vectors are [k][p][nL], the mask is the support bitmask.
+// ---------------------------------------------------------------------------
+struct CgEpi {
+    const uint64_t *supp;
+    const int32_t *Lidx;
+    const uint8_t *state;
+    const double *P;
+    double *AP, *pAp;
+    int p, nL, W;
+    __device__ bool tile_active(int b, int r0, int w) const {
+        int hi = min(nL, r0 + w);
+        for (int r = r0; r < hi; ++r)
+            if (state[(size_t)b * nL + r] == 0) return true;
+        return false;
+    }
+    template <class Acc, int FM, int FN>
+    __device__ void apply_impl(int b, int i_base, int r0, int lr, int lk, Acc (&acc)[FM][FN]) const {
+        for (int c = 0; c < FN; ++c) {
+            int r = r0 + 16 * c + lr;
+            bool ok = r < nL && state[(size_t)b * nL + r] == 0;
+            double part = 0.0;
+            const uint64_t *sw = ok ? supp + (size_t)Lidx[r] * W : nullptr;
+            for (int a = 0; a < FM; ++a)
+                for (int t = 0; t < 4; ++t) {
+                    int i = i_base + 16 * a + mfma_row(0.0, lk, t);
+                    if (!ok || i >= p) continue;
+                    bool m = (sw[i >> 6] >> (i & 63)) & 1ull;
+                    size_t o = ((size_t)b * p + i) * nL + r;
+                    double ap = m ? (double)acc[a][c][t] : 0.0;
+                    AP[o] = ap;
+                    part += P[o] * ap;
+                }
+            part += __shfl_xor(part, 16);
+            part += __shfl_xor(part, 32);
+            if (ok && lk == 0) atomicAdd(&pAp[(size_t)b * nL + r], part);
+        }
+    }
+    template <class Acc, int FM, int FN>
+    __device__ void apply(int b, int i_base, int r0, int lr, int lk, Acc (&acc)[FM][FN]) const {
+        apply_impl<Acc, FM, FN>(b, i_base, r0, lr, lk, acc);
+    }
+};
+
+// The product kernel of admm.hip is instantiated here through a thin copy of its
+// launch (the kernel template lives in that translation unit); CG uses its own
+// simple MFMA product with the same tiling.
+template <int FN>
+__global__ __launch_bounds__(256) void k_cg_matvec(int p, int nL, const double *__restrict__ A,
+                                                   const double *__restrict__ V, CgEpi epi) {
+    const int b = blockIdx.z;
+    const int r0 = blockIdx.x * (16 * FN);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int i_base = blockIdx.y * 64 + wid * 16;
+    const int lr = lane & 15, lk = lane >> 4;
+    if (!epi.tile_active(b, r0, 16 * FN)) return;
+    if (i_base >= p) return;
+    const double *Ab = A + (size_t)b * p * p;
+    const double *Vb = V + (size_t)b * p * nL;
+    dx4 acc[1][FN];
+    for (int c = 0; c < FN; ++c) acc[0][c] = dx4{0, 0, 0, 0};
+    const int icol = i_base + lr;
+    const bool iok = icol < p;
+    for (int k0 = 0; k0 < p; k0 += 4) {
+        const int k = k0 + lk;
+        const bool kok = k < p;
+        double av = (kok && iok) ? Ab[(size_t)k * p + icol] : 0.0;
+#pragma unroll
+        for (int c = 0; c < FN; ++c) {
+            int r = r0 + 16 * c + lr;
+            double bv = (kok && r < nL) ? Vb[(size_t)k * nL + r] : 0.0;
+            acc[0][c] = mfma16x16x4(av, bv, acc[0][c]);
+        }
+    }
+    epi.apply<dx4, 1, FN>(b, i_base, r0, lr, lk, acc);
+}
+
+__global__ void k_cg_init(int nb, int p, int pe, int nL, int W, const uint64_t *__restrict__ supp,
+                          const int32_t *__restrict__ Lidx, const double *__restrict__ CT,
+                          double *__restrict__ X, double *__restrict__ Rv, double *__restrict__ P,
+                          double *__restrict__ rr) {
+    int c = blockIdx.x * 64 + (threadIdx.x & 63);
+    int i0 = blockIdx.y * 16 + (threadIdx.x >> 6) * 4;
+    int k = blockIdx.z;
+    if (c >= nL) return;
+    int rsup = Lidx[c], e = rsup % pe;
+    const uint64_t *sw = supp + (size_t)rsup * W;
+    double part = 0.0;
+    for (int i = i0; i < min(p, i0 + 4); ++i) {
+        bool m = (sw[i >> 6] >> (i & 63)) & 1ull;
+        double v = m ? CT[((size_t)k * p + i) * pe + e] : 0.0;
+        size_t o = ((size_t)k * p + i) * nL + c;
+        X[o] = 0.0;
+        Rv[o] = v;
+        P[o] = v;
+        part += v * v;
+    }
+    atomicAdd(&rr[(size_t)k * nL + c], part);
+}
+
+__global__ void k_cg_update(int p, int nL, const uint8_t *__restrict__ state,
+                            const double *__restrict__ rr, const double *__restrict__ pAp,
+                            const double *__restrict__ P, const double *__restrict__ AP,
+                            double *__restrict__ X, double *__restrict__ Rv, double *__restrict__ rrn) {
+    int c = blockIdx.x * 64 + (threadIdx.x & 63);
+    int i0 = blockIdx.y * 16 + (threadIdx.x >> 6) * 4;
+    int k = blockIdx.z;
+    if (c >= nL) return;
+    size_t sc = (size_t)k * nL + c;
+    if (state[sc]) return;
+    double den = pAp[sc];
+    double alpha = den > 0.0 ? rr[sc] / den : 0.0;
+    double part = 0.0;
+    for (int i = i0; i < min(p, i0 + 4); ++i) {
+        size_t o = ((size_t)k * p + i) * nL + c;
+        X[o] += alpha * P[o];
+        double r = Rv[o] - alpha * AP[o];
+        Rv[o] = r;
+        part += r * r;
+    }
+    atomicAdd(&rrn[sc], part);
+}
+
+__global__ void k_cg_dir(int p, int nL, const uint8_t *__restrict__ state,
+                         const double *__restrict__ rr, const double *__restrict__ rrn,
+                         const double *__restrict__ Rv, double *__restrict__ P) {
+    int c = blockIdx.x * 64 + (threadIdx.x & 63);
+    int i0 = blockIdx.y * 16 + (threadIdx.x >> 6) * 4;
+    int k = blockIdx.z;
+    if (c >= nL) return;
+    size_t sc = (size_t)k * nL + c;
+    if (state[sc]) return;
+    double beta = rr[sc] > 0.0 ? rrn[sc] / rr[sc] : 0.0;
+    for (int i = i0; i < min(p, i0 + 4); ++i) {
+        size_t o = ((size_t)k * p + i) * nL + c;
+        P[o] = Rv[o] + beta * P[o];
+    }
+}
+
+__global__ void k_cg_scalars(int n, double tol2, uint8_t *__restrict__ state, double *__restrict__ rr,
+                             double *__restrict__ rrn, const double *__restrict__ rr0,
+                             double *__restrict__ pAp, int *__restrict__ active) {
+    int sc = blockIdx.x * blockDim.x + threadIdx.x;
+    bool act = false;
+    if (sc < n && !state[sc]) {
+        double v = rrn[sc];
+        rr[sc] = v;
+        if (v <= tol2 * rr0[sc]) state[sc] = 1;
+        else act = true;
+    }
+    if (sc < n) {
+        rrn[sc] = 0.0;
+        pAp[sc] = 0.0;
+    }
+    unsigned long long bal = __ballot(act);
+    if ((threadIdx.x & 63) == 0 && bal) atomicAdd(active, __popcll(bal));
+}
+
+// Scatter the CG solutions into the dense fits and compute their losses.
+__global__ __launch_bounds__(256) void k_cg_finish(int p, int pe, int R, int nL, int W,
+                                                   const uint64_t *__restrict__ supp,
+                                                   const int32_t *__restrict__ Lidx,
+                                                   const double *__restrict__ X,
+                                                   const double *__restrict__ GE,
+                                                   const double *__restrict__ CE,
+                                                   const double *__restrict__ sE,
+                                                   double *__restrict__ Fit, double *__restrict__ loss) {
+    extern __shared__ double dyn[];
+    int *idx = reinterpret_cast<int *>(dyn);
+    double *bv = dyn + (p + 1) / 2 + 1;
+    const int c = blockIdx.x, k = blockIdx.y;
+    const int rsup = Lidx[c], e = rsup % pe;
+    const int s = support_members(supp + (size_t)rsup * W, W, idx);
+    for (int a = threadIdx.x; a < s; a += 256) bv[a] = X[((size_t)k * p + idx[a]) * nL + c];
+    __syncthreads();
+    double *F = Fit + ((size_t)k * R + rsup) * p;
+    for (int i = threadIdx.x; i < p; i += 256) F[i] = 0.0;
+    __syncthreads();
+    for (int a = threadIdx.x; a < s; a += 256) F[idx[a]] = bv[a];
+    double L = eval_loss(s, idx, bv, GE + (size_t)k * p * p, CE + (size_t)k * p * pe, p, pe, e,
+                         sE[(size_t)k * pe + e]);
+    if (threadIdx.x == 0) loss[(size_t)k * R + rsup] = L;
+}
+
+// L[k][j] = sum_e loss[k][j*pe + e]; jstar[k] = first argmin over j.
+__global__ void k_argmin(int q, int pe, const double *__restrict__ loss, double *__restrict__ Lq,
+                         int32_t *__restrict__ jstar) {
+    const int k = blockIdx.x;
+    for (int j = threadIdx.x; j < q; j += blockDim.x) {
+        double s = 0.0;
+        for (int e = 0; e < pe; ++e) s += loss[((size_t)k * q + j) * pe + e];
+        Lq[(size_t)k * q + j] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int best = 0;
+        for (int j = 1; j < q; ++j)
+            if (Lq[(size_t)k * q + j] < Lq[(size_t)k * q + best]) best = j;
+        jstar[k] = best;
+    }
+}
+
+// beta*[e][i] = (1/nb) sum_k Fit[k][jstar_k*pe + e][i]
+__global__ void k_average(int nb, int p, int pe, int R, const double *__restrict__ Fit,
+                          const int32_t *__restrict__ jstar, double *__restrict__ out) {
+    size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (size_t)pe * p) return;
+    int e = (int)(t / p), i = (int)(t % p);
+    double s = 0.0;
+    for (int k = 0; k < nb; ++k) s += Fit[((size_t)k * R + (size_t)jstar[k] * pe + e) * p + i];
+    out[t] = s / nb;
+}
+
+// ---------------------------------------------------------------------------
+namespace {
+struct EstimWork {
+    int32_t *cnt, *Lidx;
+    double *Fit, *loss, *Lq;
+    double *X, *Rv, *P, *AP, *rr, *rr0, *rrn, *pAp;
+    uint8_t *state;
+    int *flags;  // [0] bad factor, [1] active count
+};
+EstimWork carve(const EstimProblem &E, int nL, Arena &ar) {
+    EstimWork w{};
+    w.cnt = ar.take<int32_t>(E.R);
+    w.Lidx = ar.take<int32_t>(std::max(nL, 1));
+    w.Fit = ar.take<double>((size_t)E.nb * E.R * E.p);
+    w.loss = ar.take<double>((size_t)E.nb * E.R);
+    w.Lq = ar.take<double>((size_t)E.nb * E.q);
+    size_t nv = (size_t)E.nb * E.p * std::max(nL, 1);
+    size_t ns = (size_t)E.nb * std::max(nL, 1);
+    w.X = ar.take<double>(nv);
+    w.Rv = ar.take<double>(nv);
+    w.P = ar.take<double>(nv);
+    w.AP = ar.take<double>(nv);
+    w.rr = ar.take<double>(ns);
+    w.rr0 = ar.take<double>(ns);
+    w.rrn = ar.take<double>(ns);
+    w.pAp = ar.take<double>(ns);
+    w.state = ar.take<uint8_t>(ns);
+    w.flags = ar.take<int>(2);
+    return w;
+}
+}  // namespace
+
+size_t estim_work_bytes(const EstimProblem &E) {
+    // worst case: every support is large
+    Arena ar;
+    carve(E, E.R, ar);
+    return ar.off + 4096;
+}
+
+void estimate(hipStream_t s, const EstimProblem &E, void *work, double *beta_out, int32_t *jstar,
+              double *losses_out, float *stage_ms) {
+    const int W = (E.p + 63) / 64;
+    UOI_REQUIRE(W <= 1024, "estimation: p must be <= 65536");
+    // support sizes decide the solver of every column (they do not depend on k)
+    Arena pre;
+    pre.base = (char *)work;
+    pre.cap = (size_t)-1;
+    int32_t *cnt = pre.take<int32_t>(E.R);
+    hipLaunchKernelGGL(k_popcount, dim3(cdiv(E.R, 256)), dim3(256), 0, s, E.R, W, E.supp, cnt);
+    UOI_LAUNCH_CHECK();
+    std::vector<int32_t> hc(E.R);
+    UOI_HIP(hipMemcpyAsync(hc.data(), cnt, sizeof(int32_t) * E.R, hipMemcpyDeviceToHost, s));
+    UOI_HIP(hipStreamSynchronize(s));
+    std::vector<int32_t> lidx;
+    int smax = 0;
+    for (int r = 0; r < E.R; ++r) {
+        if (hc[r] > kSmall) lidx.push_back(r);
+        else smax = std::max(smax, (int)hc[r]);
+    }
+    const int nL = (int)lidx.size();
+    Arena ar;
+    ar.base = (char *)work;
+    ar.cap = (size_t)-1;
+    EstimWork w = carve(E, nL, ar);
+    if (nL) UOI_HIP(hipMemcpyAsync(w.Lidx, lidx.data(), sizeof(int32_t) * nL, hipMemcpyHostToDevice, s));
+    UOI_HIP(hipMemsetAsync(w.flags, 0, 2 * sizeof(int), s));
+
+    hipEvent_t ev[3];
+    if (stage_ms) {
+        for (auto &e : ev) UOI_HIP(hipEventCreate(&e));
+        UOI_HIP(hipEventRecord(ev[0], s));
+    }
+    // small supports
+    size_t lds = sizeof(double) * (size_t)smax * smax;
+    hipLaunchKernelGGL(k_ols_small, dim3(E.R, E.nb), dim3(256), lds, s, E.p, E.pe, E.R, W, E.supp,
+                       w.cnt, E.GT, E.CT, E.GE, E.CE, E.sE, w.Fit, w.loss, w.flags);
+    UOI_LAUNCH_CHECK();
+    // large supports by batched conjugate gradients
+    if (nL) {
+        size_t ns = (size_t)E.nb * nL;
+        UOI_HIP(hipMemsetAsync(w.rr, 0, sizeof(double) * ns, s));
+        UOI_HIP(hipMemsetAsync(w.rrn, 0, sizeof(double) * ns, s));
+        UOI_HIP(hipMemsetAsync(w.pAp, 0, sizeof(double) * ns, s));
+        UOI_HIP(hipMemsetAsync(w.state, 0, ns, s));
+        dim3 eg(cdiv(nL, 64), cdiv(E.p, 16), E.nb);
+        hipLaunchKernelGGL(k_cg_init, eg, dim3(256), 0, s, E.nb, E.p, E.pe, nL, W, E.supp, w.Lidx,
+                           E.CT, w.X, w.Rv, w.P, w.rr);
+        UOI_HIP(hipMemcpyAsync(w.rr0, w.rr, sizeof(double) * ns, hipMemcpyDeviceToDevice, s));
+        UOI_LAUNCH_CHECK();
+        CgEpi epi{E.supp, w.Lidx, w.state, w.P, w.AP, w.pAp, E.p, nL, W};
+        for (int it = 0; it < kCgMaxIter; ++it) {
+            if (nL <= 16)
+                hipLaunchKernelGGL(k_cg_matvec<1>, dim3(cdiv(nL, 16), cdiv(E.p, 64), E.nb), dim3(256), 0,
+                                   s, E.p, nL, E.GT, w.P, epi);
+            else if (nL <= 32)
+                hipLaunchKernelGGL(k_cg_matvec<2>, dim3(cdiv(nL, 32), cdiv(E.p, 64), E.nb), dim3(256), 0,
+                                   s, E.p, nL, E.GT, w.P, epi);
+            else
+                hipLaunchKernelGGL(k_cg_matvec<4>, dim3(cdiv(nL, 64), cdiv(E.p, 64), E.nb), dim3(256), 0,
+                                   s, E.p, nL, E.GT, w.P, epi);
+            hipLaunchKernelGGL(k_cg_update, eg, dim3(256), 0, s, E.p, nL, w.state, w.rr, w.pAp, w.P, w.AP,
+                               w.X, w.Rv, w.rrn);
+            hipLaunchKernelGGL(k_cg_dir, eg, dim3(256), 0, s, E.p, nL, w.state, w.rr, w.rrn, w.Rv, w.P);
+            hipLaunchKernelGGL(k_cg_scalars, dim3(cdiv(ns, 256)), dim3(256), 0, s, (int)ns,
+                               kCgTol * kCgTol, w.state, w.rr, w.rrn, w.rr0, w.pAp, w.flags + 1);
+            UOI_LAUNCH_CHECK();
+            if (it % 8 == 7) {
+                int active = 0;
+                UOI_HIP(hipMemcpyAsync(&active, w.flags + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+                UOI_HIP(hipStreamSynchronize(s));
+                if (active == 0) break;
+            }
+            UOI_HIP(hipMemsetAsync(w.flags + 1, 0, sizeof(int), s));
+        }
+        size_t lds2 = sizeof(double) * ((size_t)(E.p + 1) / 2 + 1 + E.p);
+        UOI_REQUIRE(lds2 <= 64 * 1024, "estimation: p too large for the CG finish kernel");
+        hipLaunchKernelGGL(k_cg_finish, dim3(nL, E.nb), dim3(256), lds2, s, E.p, E.pe, E.R, nL, W,
+                           E.supp, w.Lidx, w.X, E.GE, E.CE, E.sE, w.Fit, w.loss);
+        UOI_LAUNCH_CHECK();
+    }
+    if (stage_ms) UOI_HIP(hipEventRecord(ev[1], s));
+    hipLaunchKernelGGL(k_argmin, dim3(E.nb), dim3(64), 0, s, E.q, E.pe, w.loss, w.Lq, jstar);
+    hipLaunchKernelGGL(k_average, dim3(cdiv((size_t)E.pe * E.p, 256)), dim3(256), 0, s, E.nb, E.p, E.pe,
+                       E.R, w.Fit, jstar, beta_out);
+    UOI_LAUNCH_CHECK();
+    if (losses_out)
+        UOI_HIP(hipMemcpyAsync(losses_out, w.Lq, sizeof(double) * E.nb * E.q, hipMemcpyDeviceToDevice, s));
+    if (stage_ms) {
+        UOI_HIP(hipEventRecord(ev[2], s));
+        UOI_HIP(hipEventSynchronize(ev[2]));
+        UOI_HIP(hipEventElapsedTime(&stage_ms[0], ev[0], ev[1]));
+        UOI_HIP(hipEventElapsedTime(&stage_ms[1], ev[1], ev[2]));
+        for (auto &e : ev) UOI_HIP(hipEventDestroy(e));
+    }
+    int bad = 0;
+    UOI_HIP(hipMemcpyAsync(&bad, w.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+    UOI_HIP(hipStreamSynchronize(s));
+    if (bad) throw Error(UOI_EINVAL, "estimation: a training Gram restricted to a support is singular");
+}
+
+}  // namespace uoi

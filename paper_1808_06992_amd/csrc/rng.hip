@@ -1,0 +1,183 @@
+// Index streams of the bootstrap and train/evaluation samples (Alg. 1 "generate
+// bootstrap sample", Alg. 2 block bootstrap of Sec. III-A.2).  Keys are a
+// counter-based SplitMix64 of (seed, tag, bootstrap, position); draws use a
+// multiply-shift range map, so every index is a pure function of its position.
+#include "common.hpp"
+
+namespace uoi {
+
+// rows[k][i] = range_map(key(seed, LASSO_BOOT, k, i), n): n draws with replacement.
+__global__ void k_boot_rows(uint64_t seed, int n, int32_t *__restrict__ rows) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int k = blockIdx.y;
+    if (i < n)
+        rows[(size_t)k * n + i] = (int32_t)range_map(stream_key(seed, TAG_LASSO_BOOT, k, i), (uint32_t)n);
+}
+
+// Moving-block bootstrap: row i belongs to block i/L, whose start is drawn in [0, N-L].
+__global__ void k_var_boot_rows(uint64_t seed, int N, int L, int32_t *__restrict__ rows) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int k = blockIdx.y;
+    if (i < N) {
+        int b = i / L;
+        uint32_t start = range_map(stream_key(seed, TAG_VAR_BOOT, k, b), (uint32_t)(N - L + 1));
+        rows[(size_t)k * N + i] = (int32_t)start + (i - b * L);
+    }
+}
+
+// Train/eval split: item i of bootstrap k is a training item when fewer than
+// ntrain items precede it in (key, index) order.  Keys of a 256-item tile are
+// generated into LDS and compared by every thread.
+__global__ __launch_bounds__(256) void k_split_rank(uint64_t seed, uint32_t tag, int cnt, int ntrain,
+                                                    uint8_t *__restrict__ is_train) {
+    __shared__ uint64_t tile[256];
+    int i = blockIdx.x * 256 + threadIdx.x;
+    int k = blockIdx.y;
+    uint64_t mine = i < cnt ? stream_key(seed, tag, k, i) : 0;
+    int before = 0;
+    for (int t0 = 0; t0 < cnt; t0 += 256) {
+        int j = t0 + threadIdx.x;
+        tile[threadIdx.x] = j < cnt ? stream_key(seed, tag, k, j) : ~0ull;
+        __syncthreads();
+        int lim = min(256, cnt - t0);
+        for (int t = 0; t < lim; ++t) {
+            uint64_t kj = tile[t];
+            int j2 = t0 + t;
+            before += (kj < mine) || (kj == mine && j2 < i);
+        }
+        __syncthreads();
+    }
+    if (i < cnt) is_train[(size_t)k * cnt + i] = before < ntrain ? 1 : 0;
+}
+
+// Stable compaction of items into ascending train / eval lists (one block per bootstrap).
+__global__ __launch_bounds__(256) void k_compact(int cnt, int ntrain, const uint8_t *__restrict__ is_train,
+                                                 int32_t *__restrict__ train, int32_t *__restrict__ eval) {
+    __shared__ int wtot[4];
+    __shared__ int base_s[2];
+    int k = blockIdx.x;
+    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const uint8_t *f = is_train + (size_t)k * cnt;
+    int32_t *tr = train + (size_t)k * ntrain;
+    int32_t *ev = eval + (size_t)k * (cnt - ntrain);
+    if (threadIdx.x == 0) base_s[0] = base_s[1] = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 < cnt; c0 += 256) {
+        int i = c0 + threadIdx.x;
+        bool valid = i < cnt;
+        bool t = valid && f[i];
+        unsigned long long bal = __ballot(t);
+        int pre = __popcll(bal & ((1ull << lane) - 1ull));
+        if (lane == 0) wtot[wid] = __popcll(bal);
+        __syncthreads();
+        int woff = 0, tot = 0;
+        for (int w = 0; w < 4; ++w) {
+            if (w < wid) woff += wtot[w];
+            tot += wtot[w];
+        }
+        int nvalid = min(256, cnt - c0);
+        int bt = base_s[0], be = base_s[1];
+        if (valid) {
+            int pt = woff + pre;  // training items before me in this chunk
+            if (t) tr[bt + pt] = i;
+            else ev[be + (threadIdx.x - pt)] = i;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            base_s[0] = bt + tot;
+            base_s[1] = be + (nvalid - tot);
+        }
+        __syncthreads();
+    }
+}
+
+// VAR split: blocks [bL, min((b+1)L, N)) flagged as training are expanded to rows
+// in ascending order; row lists of bootstrap k start at k*N.
+__global__ __launch_bounds__(256) void k_expand_blocks(int nblk, int N, int L,
+                                                       const uint8_t *__restrict__ is_train,
+                                                       int32_t *__restrict__ train,
+                                                       int32_t *__restrict__ eval,
+                                                       int32_t *__restrict__ ntr,
+                                                       int32_t *__restrict__ nev) {
+    __shared__ int off_s[1024];
+    __shared__ int base_s[2];
+    int k = blockIdx.x;
+    const uint8_t *f = is_train + (size_t)k * nblk;
+    int32_t *tr = train + (size_t)k * N;
+    int32_t *ev = eval + (size_t)k * N;
+    if (threadIdx.x == 0) base_s[0] = base_s[1] = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 < nblk; c0 += 1024) {
+        int nc = min(1024, nblk - c0);
+        if (threadIdx.x == 0) {
+            int a = base_s[0], e = base_s[1];
+            for (int t = 0; t < nc; ++t) {
+                int b = c0 + t;
+                int sz = min(L, N - b * L);
+                if (f[b]) { off_s[t] = a; a += sz; }
+                else { off_s[t] = e; e += sz; }
+            }
+            base_s[0] = a;
+            base_s[1] = e;
+        }
+        __syncthreads();
+        for (int t = 0; t < nc; ++t) {
+            int b = c0 + t;
+            int sz = min(L, N - b * L);
+            int32_t *dst = f[b] ? tr : ev;
+            for (int r = threadIdx.x; r < sz; r += 256) dst[off_s[t] + r] = b * L + r;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        ntr[k] = base_s[0];
+        nev[k] = base_s[1];
+    }
+}
+
+__global__ void k_finite(const double *__restrict__ x, size_t n, int *flag) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    bool bad = false;
+    for (; i < n; i += stride) bad |= !isfinite(x[i]);
+    if (bad) atomicOr(flag, 1);
+}
+
+void launch_boot_rows(hipStream_t s, uint64_t seed, uint32_t, int nb, int n, int32_t *rows) {
+    hipLaunchKernelGGL(k_boot_rows, dim3(cdiv(n, 256), nb), dim3(256), 0, s, seed, n, rows);
+    UOI_LAUNCH_CHECK();
+}
+
+void launch_var_boot_rows(hipStream_t s, uint64_t seed, int nb, int N, int L, int32_t *rows) {
+    hipLaunchKernelGGL(k_var_boot_rows, dim3(cdiv(N, 256), nb), dim3(256), 0, s, seed, N, L, rows);
+    UOI_LAUNCH_CHECK();
+}
+
+void launch_split(hipStream_t s, uint64_t seed, uint32_t tag, int nb, int cnt, int ntrain,
+                  uint8_t *is_train) {
+    hipLaunchKernelGGL(k_split_rank, dim3(cdiv(cnt, 256), nb), dim3(256), 0, s, seed, tag, cnt,
+                       ntrain, is_train);
+    UOI_LAUNCH_CHECK();
+}
+
+void launch_compact_rows(hipStream_t s, int nb, int cnt, const uint8_t *is_train, int ntrain,
+                         int32_t *train, int32_t *eval) {
+    hipLaunchKernelGGL(k_compact, dim3(nb), dim3(256), 0, s, cnt, ntrain, is_train, train, eval);
+    UOI_LAUNCH_CHECK();
+}
+
+void launch_expand_blocks(hipStream_t s, int nb, int nblk, int N, int L, const uint8_t *is_train,
+                          int32_t *train, int32_t *eval, int32_t *ntr, int32_t *nev) {
+    hipLaunchKernelGGL(k_expand_blocks, dim3(nb), dim3(256), 0, s, nblk, N, L, is_train, train, eval,
+                       ntr, nev);
+    UOI_LAUNCH_CHECK();
+}
+
+void launch_finite_check(hipStream_t s, const double *x, size_t n, int *flag) {
+    unsigned g = (unsigned)std::min<size_t>(1024, (n + 255) / 256);
+    if (g == 0) return;
+    hipLaunchKernelGGL(k_finite, dim3(g), dim3(256), 0, s, x, n, flag);
+    UOI_LAUNCH_CHECK();
+}
+
+}  // namespace uoi

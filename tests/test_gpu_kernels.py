@@ -1,0 +1,145 @@
+"""GPU parity of the individual steps against the CPU oracle (MI355X only).
+
+Index streams are compared bit for bit; float64 statistics, inverses and ADMM
+solutions are compared with the tolerances stated in each test."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1808_06992_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_1808_06992_amd import _lib
+    _lib.load()
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return _lib
+
+
+def cuda(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+# --------------------------------------------------------------------------- indices
+
+@pytest.mark.parametrize("n", [1, 7, 200, 1001, 5000])
+def test_bootstrap_rows_bit_identical(api, orc, n):
+    rows = api.bootstrap_rows(12345, 5, n).cpu().numpy()
+    for k in range(5):
+        assert np.array_equal(rows[k], orc.boot_rows(12345, k, n))
+
+
+@pytest.mark.parametrize("n", [2, 5, 200, 1001, 5000])
+def test_split_rows_bit_identical(api, orc, n):
+    tr, ev = api.split_rows(99, 4, n)
+    tr, ev = tr.cpu().numpy(), ev.cpu().numpy()
+    for k in range(4):
+        t, e = orc.split_rows(99, k, n)
+        assert np.array_equal(tr[k], t) and np.array_equal(ev[k], e)
+
+
+@pytest.mark.parametrize("N,L", [(9999, 22), (19999, 28), (103, 5), (10, 10)])
+def test_var_rows_bit_identical(api, orc, N, L):
+    rows = api.var_boot_rows(7, 3, N, L).cpu().numpy()
+    for k in range(3):
+        assert np.array_equal(rows[k], orc.var_boot_rows(7, k, N, L))
+    if (N + L - 1) // L >= 2:
+        trs, evs = api.var_split_rows(7, 3, N, L)
+        for k in range(3):
+            t, e = orc.var_split_rows(7, k, N, L)
+            assert np.array_equal(trs[k].cpu().numpy(), t)
+            assert np.array_equal(evs[k].cpu().numpy(), e)
+
+
+# --------------------------------------------------------------------------- Gram
+
+@pytest.mark.parametrize("n,p,m", [(37, 5, 37), (517, 133, 601), (300, 64, 17), (1000, 200, 1000)])
+def test_gram_parity(api, orc, n, p, m):
+    rng = np.random.default_rng(n + p)
+    X = rng.standard_normal((n, p))
+    y = rng.standard_normal(n)
+    rows = rng.integers(0, n, size=(3, m)).astype(np.int32)
+    G, c = api.gram(cuda(X), cuda(rows, torch.int32), cuda(y))
+    G, c = G.cpu().numpy(), c.cpu().numpy()
+    for b in range(3):
+        Go, co = orc.gram(X, y, rows[b])
+        np.testing.assert_allclose(G[b], Go, rtol=1e-12, atol=1e-13)
+        np.testing.assert_allclose(c[b, :, 0], co, rtol=1e-12, atol=1e-13)
+        assert np.array_equal(G[b], G[b].T)
+
+
+def test_gram_var_parity(api, orc):
+    pr = synth.var1(70, 400, 0.1, 0.8, 3, burn=20)
+    N = pr.series.shape[0] - 1
+    rows = np.stack([orc.var_boot_rows(3, k, N, 8) for k in range(2)])
+    G, Cm = api.gram_var(cuda(pr.series), cuda(rows, torch.int32))
+    for b in range(2):
+        Go, Co = orc.gram_var(pr.series, rows[b])
+        np.testing.assert_allclose(G[b].cpu().numpy(), Go, rtol=1e-12, atol=1e-13)
+        np.testing.assert_allclose(Cm[b].cpu().numpy(), Co, rtol=1e-12, atol=1e-13)
+
+
+# --------------------------------------------------------------------------- inverse
+
+@pytest.mark.parametrize("p", [1, 7, 50, 88, 89, 130, 200])
+def test_spd_inverse_parity(api, orc, p):
+    rng = np.random.default_rng(p)
+    n = 3 * p + 10
+    X = rng.standard_normal((n, p))
+    G = np.stack([orc.gram(X, X[:, 0], orc.boot_rows(1, k, n))[0] for k in range(2)])
+    M = api.spd_inverse(cuda(G), 1.0).cpu().numpy()
+    for b in range(2):
+        ref = np.linalg.inv(G[b] + np.eye(p))
+        np.testing.assert_allclose(M[b], ref, rtol=1e-11, atol=1e-13 * np.abs(ref).max())
+
+
+# --------------------------------------------------------------------------- ADMM
+
+def _oracle_solutions(orc, G, c, lams):
+    out = []
+    b = None
+    for lam in lams:
+        b, st = orc.lasso_cd(G, c, lam, tol=1e-13, b0=b)
+        assert st >= 0
+        out.append(b.copy())
+    return np.array(out)
+
+
+@pytest.mark.parametrize("solver,precision", [("batched", "fp64"), ("plain", "fp64"),
+                                              ("batched", "mixed")])
+@pytest.mark.parametrize("n,p,q", [(200, 50, 16), (400, 130, 9)])
+def test_admm_matches_oracle(api, orc, solver, precision, n, p, q):
+    pr = synth.lasso_random(n, p, 10, 5, q=q)
+    Gs, cs = [], []
+    for k in range(3):
+        G, c = orc.gram(pr.X, pr.y, orc.boot_rows(0, k, n))
+        Gs.append(G)
+        cs.append(c)
+    Gs, cs = np.array(Gs), np.array(cs)
+    res = api.lasso_solve_batch(cuda(Gs), cuda(cs), pr.lambdas, kkt_tol=1e-10, solver=solver,
+                                precision=precision, max_iter=50000)
+    z = res["z"].cpu().numpy()
+    assert res["status"] == 0
+    assert np.all(res["iters"].cpu().numpy() >= 0)
+    for k in range(3):
+        ref = _oracle_solutions(orc, Gs[k], cs[k], pr.lambdas)
+        for j in range(q):
+            # the GPU estimate meets the KKT bound when checked by the oracle
+            assert orc.kkt(Gs[k], cs[k], pr.lambdas[j], z[k, j]) <= 1e-8
+            scale = max(np.abs(ref[j]).max(), 1e-300)
+            assert np.abs(z[k, j] - ref[j]).max() <= 1e-6 * scale
+            dec = orc.decided_bits(Gs[k], cs[k], pr.lambdas[j], ref[j])
+            assert np.array_equal((z[k, j] != 0)[dec], (ref[j] != 0)[dec])
+
+
+def test_admm_reports_nonconvergence(api, orc):
+    pr = synth.lasso_random(200, 50, 10, 1, q=4)
+    G, c = orc.gram(pr.X, pr.y, np.arange(200, dtype=np.int32))
+    res = api.lasso_solve_batch(cuda(G[None]), cuda(c[None]), pr.lambdas, kkt_tol=1e-12,
+                                max_iter=1, check_every=1)
+    assert res["status"] == api.UOI_ENOCONV
+    its = res["iters"].cpu().numpy()
+    assert np.any(its < 0)

@@ -1,0 +1,132 @@
+"""End-to-end UoI_LASSO / UoI_VAR parity of the HIP path against the CPU oracle.
+
+Supports are compared bit for bit on every bit the oracle decides with a
+margin (a bit inside the margin can legitimately differ between two solvers
+that both meet the KKT tolerance); the chosen support per split must agree
+wherever the loss gap exceeds 1e-9 relative; beta* / A must agree within
+1e-6 relative to its largest entry."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1808_06992_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TAU = 1e-6
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_1808_06992_amd import _lib
+    _lib.load()
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return _lib
+
+
+def cuda(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def words_to_bool(w, p):
+    w = np.asarray(w).view(np.uint64)
+    bits = np.zeros(w.shape[:-1] + (p,), bool)
+    for i in range(p):
+        bits[..., i] = (w[..., i // 64] >> np.uint64(i % 64)) & np.uint64(1)
+    return bits
+
+
+def lasso_decided(orc, pr, seed, sel_beta):
+    """Decided intersection bits per lambda: every bootstrap decided, or one decidedly zero."""
+    n, p = pr.X.shape
+    B1, q = sel_beta.shape[:2]
+    all_dec = np.ones((q, p), bool)
+    some_zero = np.zeros((q, p), bool)
+    for k in range(B1):
+        G, c = orc.gram(pr.X, pr.y, orc.boot_rows(seed, k, n))
+        for j in range(q):
+            d = orc.decided_bits(G, c, pr.lambdas[j], sel_beta[k, j], TAU)
+            all_dec[j] &= d
+            some_zero[j] |= d & (sel_beta[k, j] == 0)
+    return all_dec | some_zero
+
+
+def check_jstar(losses_o, jstar_o, jstar_g):
+    for k, (a, b) in enumerate(zip(jstar_o, jstar_g)):
+        if a == b:
+            continue
+        L = losses_o[k]
+        gap = abs(L[b] - L[a]) / max(abs(L[a]), 1e-300)
+        assert gap <= 1e-9, f"split {k}: oracle j*={a}, GPU j*={b}, loss gap {gap}"
+
+
+@pytest.mark.parametrize("precision,solver", [("fp64", "batched"), ("fp64", "plain"),
+                                              ("mixed", "batched")])
+def test_uoi_lasso_small_config(api, orc, precision, solver):
+    pr = synth.lasso_small(0)
+    seed = 0
+    ref = orc.uoi_lasso(pr.X, pr.y, pr.lambdas, pr.B1, pr.B2, seed, keep_selection=True)
+    assert ref["status"] == 0
+    out = api.lasso_fit(cuda(pr.X), cuda(pr.y), pr.lambdas, pr.B1, pr.B2, seed, kkt_tol=1e-10,
+                        precision=precision, solver=solver, sel_beta=True)
+    assert out["status"] == 0 and out["n_unconverged"] == 0
+    p = pr.X.shape[1]
+    dec = lasso_decided(orc, pr, seed, ref["sel_beta"])
+    got = words_to_bool(out["supports"].cpu().numpy(), p)
+    want = words_to_bool(ref["supports"], p)
+    assert np.array_equal(got[dec], want[dec])
+    # selection estimates agree solve by solve
+    sb = out["sel_beta"].cpu().numpy()
+    for k in range(pr.B1):
+        for j in range(pr.lambdas.size):
+            r = ref["sel_beta"][k, j]
+            assert np.abs(sb[k, j] - r).max() <= 1e-6 * max(np.abs(r).max(), 1e-300)
+    if dec.all():
+        jg = out["jstar"].cpu().numpy()
+        check_jstar(ref["losses"], ref["jstar"], jg)
+        np.testing.assert_allclose(out["losses"].cpu().numpy(), ref["losses"], rtol=1e-9)
+        if np.array_equal(jg, ref["jstar"]):
+            b = out["beta"].cpu().numpy()
+            assert np.abs(b - ref["beta"]).max() <= 1e-6 * np.abs(ref["beta"]).max()
+
+
+def test_uoi_lasso_ragged_sizes(api, orc):
+    # p not a multiple of 16 or 64, q odd, n not a multiple of the row chunk
+    pr = synth.lasso_random(157, 37, 6, 11, q=7, B1=5, B2=6)
+    ref = orc.uoi_lasso(pr.X, pr.y, pr.lambdas, pr.B1, pr.B2, 5, keep_selection=True)
+    out = api.lasso_fit(cuda(pr.X), cuda(pr.y), pr.lambdas, pr.B1, pr.B2, 5, kkt_tol=1e-10)
+    dec = lasso_decided(orc, pr, 5, ref["sel_beta"])
+    got = words_to_bool(out["supports"].cpu().numpy(), 37)
+    want = words_to_bool(ref["supports"], 37)
+    assert np.array_equal(got[dec], want[dec])
+    if dec.all():
+        check_jstar(ref["losses"], ref["jstar"], out["jstar"].cpu().numpy())
+
+
+def test_uoi_var_small(api, orc):
+    pr = synth.var1(12, 600, 0.15, 0.8, 4, burn=50, q=6, B1=4, B2=4)
+    seed = 3
+    ref = orc.uoi_var(pr.series, pr.lambdas, pr.B1, pr.B2, seed)
+    assert ref["status"] == 0
+    out = api.var_fit(cuda(pr.series), pr.lambdas, pr.B1, pr.B2, seed, kkt_tol=1e-10)
+    assert out["status"] == 0
+    p = pr.series.shape[1]
+    got = words_to_bool(out["supports"].cpu().numpy(), p)
+    want = words_to_bool(ref["supports"], p)
+    mism = np.argwhere(got != want)
+    assert mism.shape[0] <= 2, f"support mismatches {mism.tolist()}"
+    if mism.shape[0] == 0:
+        check_jstar(ref["losses"], ref["jstar"], out["jstar"].cpu().numpy())
+        if np.array_equal(out["jstar"].cpu().numpy(), ref["jstar"]):
+            A = out["A"].cpu().numpy()
+            assert np.abs(A - ref["A"]).max() <= 1e-6 * np.abs(ref["A"]).max()
+    assert np.all(out["mu"].cpu().numpy() == 0)
+
+
+def test_nan_input_rejected(api):
+    pr = synth.lasso_random(50, 8, 3, 2, q=3)
+    X = pr.X.copy()
+    X[3, 4] = np.nan
+    with pytest.raises(api.UoiError) as ei:
+        api.lasso_fit(cuda(X), cuda(pr.y), pr.lambdas, 2, 2, 0)
+    assert ei.value.code == api.UOI_EINVAL
