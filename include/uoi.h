@@ -98,6 +98,28 @@ typedef struct uoi_opts {
     void *stream;          /* hipStream_t, NULL = default stream                           */
 } uoi_opts;
 
+/* Per-kernel totals gathered with UOI_FLAG_TIMING: device time from hipEvents
+ * recorded on opts->stream around the launches, and the ALGORITHMIC bytes and
+ * flops of those launches (bytes: every operand the kernel must read or write
+ * once; flops: 2 per multiply-add of useful work).  Slots: */
+enum {
+    UOI_KSTAT_ADMM64 = 0, /* batched ADMM iteration, float64: per bootstrap with an active
+                             solve p*p*8 bytes of M, per active solve 4*p*8 bytes of z,u
+                             (read and write); 2*p*p flops per active solve                  */
+    UOI_KSTAT_ADMM32 = 1, /* the same in float32 (4-byte M and state)                      */
+    UOI_KSTAT_PLAIN = 2,  /* one-solve-per-workgroup kernel: per solve and iteration p*p*8
+                             bytes of M and 2*p*p flops (plus the Gram at each check)       */
+    UOI_KSTAT_GRAM = 3,   /* selection Gram: m*(p+pe)*8 bytes of gathered rows + p*(p+pe)*8
+                             bytes of output per bootstrap; m*p*(p+1) + 2*m*p*pe flops     */
+    UOI_KSTAT_N = 4
+};
+typedef struct uoi_kstat {
+    double ms;        /* summed device time of the launches             */
+    double bytes;     /* summed algorithmic bytes                       */
+    double flops;     /* summed algorithmic flops                       */
+    int64_t launches; /* number of launches                             */
+} uoi_kstat;
+
 /* Optional diagnostics.  Array members are DEVICE pointers owned by the caller
  * and may be NULL; scalar members are written by the library.  A selection
  * solve is indexed s = k*R + r, with R = q for LASSO and R = q*p for VAR
@@ -112,6 +134,7 @@ typedef struct uoi_diag {
     int32_t max_iters;  /* largest iteration count among converged solves               */
     float stage_ms[8];  /* with UOI_FLAG_TIMING: index/gram, factor, admm, verify,
                            support, estimation-gram, ols, loss+average                   */
+    uoi_kstat kstat[UOI_KSTAT_N]; /* with UOI_FLAG_TIMING: per-kernel totals (see below) */
 } uoi_diag;
 
 /* Fill *o with the defaults listed above (B1 = B2 = q = 0, lambdas = NULL). */

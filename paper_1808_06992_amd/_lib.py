@@ -47,12 +47,25 @@ class Opts(C.Structure):
     ]
 
 
+class KStat(C.Structure):
+    _fields_ = [("ms", C.c_double), ("bytes", C.c_double), ("flops", C.c_double),
+                ("launches", C.c_int64)]
+
+
+KSTATS = ("admm64", "admm32", "plain", "gram")
+
+
 class Diag(C.Structure):
     _fields_ = [
         ("iters", C.c_void_p), ("kkt", C.c_void_p), ("sel_beta", C.c_void_p),
         ("losses", C.c_void_p), ("n_solves", C.c_int64), ("n_unconverged", C.c_int64),
-        ("max_iters", C.c_int32), ("stage_ms", C.c_float * 8),
+        ("max_iters", C.c_int32), ("stage_ms", C.c_float * 8), ("kstat", KStat * 4),
     ]
+
+
+def kstats(d: Diag) -> dict:
+    return {name: dict(ms=d.kstat[i].ms, bytes=d.kstat[i].bytes, flops=d.kstat[i].flops,
+                       launches=int(d.kstat[i].launches)) for i, name in enumerate(KSTATS)}
 
 
 EXPORTS = (
@@ -172,6 +185,7 @@ def lasso_fit(X: torch.Tensor, y: torch.Tensor, lambdas, B1: int, B2: int, seed:
     out["n_unconverged"] = int(d.n_unconverged)
     out["max_iters"] = int(d.max_iters)
     out["stage_ms"] = dict(zip(STAGES, list(d.stage_ms)))
+    out["kstat"] = kstats(d)
     return out
 
 
@@ -205,6 +219,7 @@ def var_fit(series: torch.Tensor, lambdas, B1: int, B2: int, seed: int = 0, *, b
     out["n_unconverged"] = int(d.n_unconverged)
     out["max_iters"] = int(d.max_iters)
     out["stage_ms"] = dict(zip(STAGES, list(d.stage_ms)))
+    out["kstat"] = kstats(d)
     return out
 
 

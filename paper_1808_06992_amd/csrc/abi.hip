@@ -136,6 +136,34 @@ static void transpose(hipStream_t s, int nb, int p, int R, const double *a, doub
     UOI_LAUNCH_CHECK();
 }
 
+// Times one launch sequence on the stream and adds it to a kernel-stat slot.
+struct KernelTimer {
+    hipStream_t s;
+    uoi_kstat *k;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    KernelTimer(hipStream_t s_, uoi_kstat *k_) : s(s_), k(k_) {
+        if (!k) return;
+        UOI_HIP(hipEventCreate(&e0));
+        UOI_HIP(hipEventCreate(&e1));
+        UOI_HIP(hipEventRecord(e0, s));
+    }
+    void done(double bytes, double flops) {
+        if (!k) return;
+        UOI_HIP(hipEventRecord(e1, s));
+        UOI_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        UOI_HIP(hipEventElapsedTime(&ms, e0, e1));
+        k->ms += ms;
+        k->bytes += bytes;
+        k->flops += flops;
+        k->launches += 1;
+    }
+    ~KernelTimer() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    }
+};
+
 struct Timer {
     hipStream_t s;
     bool on;
@@ -174,6 +202,7 @@ static int lasso_fit(int n, int p, const double *X, const double *y, const uoi_o
     check_finite(s, y, (size_t)n, "y");
     const bool timing = (o->flags & UOI_FLAG_TIMING) != 0;
     float sm[8] = {0};
+    if (diag) std::memset(diag->kstat, 0, sizeof(diag->kstat));
 
     const int B1 = o->B1, B2 = o->B2, q = o->q, R = q;
     AdmmProblem P{B1, p, q, 1, R, nullptr, nullptr, nullptr, o->rho, o->kkt_tol, o->max_iter,
@@ -220,12 +249,18 @@ static int lasso_fit(int n, int p, const double *X, const double *y, const uoi_o
     UOI_HIP(hipMemcpyAsync(lam, o->lambdas, sizeof(double) * q, hipMemcpyHostToDevice, s));
     // model selection: bootstrap rows, Gram, ADMM sweep, supports
     launch_boot_rows(s, o->seed, TAG_LASSO_BOOT, B1, n, rows);
-    launch_gram_f64(s, B1, n, rows, nullptr, p, X, p, 1, y, 1, G, c);
+    {
+        KernelTimer kt(s, timing && diag ? &diag->kstat[UOI_KSTAT_GRAM] : nullptr);
+        launch_gram_f64(s, B1, n, rows, nullptr, p, X, p, 1, y, 1, G, c);
+        kt.done((double)B1 * ((double)n * (p + 1) * 8 + (double)p * (p + 1) * 8),
+                (double)B1 * ((double)n * p * (p + 1) + 2.0 * n * p));
+    }
     tm.mark();
     P.G = G;
     P.C = c;
     P.lam = lam;
-    AdmmOut out{z, u, diag && diag->iters ? diag->iters : its, diag && diag->kkt ? diag->kkt : kkt, 0, 0};
+    AdmmOut out{z, u, diag && diag->iters ? diag->iters : its, diag && diag->kkt ? diag->kkt : kkt, 0, 0,
+                timing && diag ? diag->kstat : nullptr};
     admm_solve(s, P, o->precision, o->solver, admm_w, false, out, timing ? sm + 1 : nullptr);
     tm.mark();
     launch_support_and(s, B1, p, R, z, supp_out);
@@ -276,6 +311,7 @@ static int var_fit(int T, int p, int d, const double *series, int block_len, con
     check_finite(s, series, (size_t)T * p, "series");
     const bool timing = (o->flags & UOI_FLAG_TIMING) != 0;
     float sm[8] = {0};
+    if (diag) std::memset(diag->kstat, 0, sizeof(diag->kstat));
 
     const int B1 = o->B1, B2 = o->B2, q = o->q, pe = p, R = q * p;
     AdmmProblem P{B1, p, q, pe, R, nullptr, nullptr, nullptr, o->rho, o->kkt_tol, o->max_iter,
@@ -323,12 +359,18 @@ static int var_fit(int T, int p, int d, const double *series, int block_len, con
     tm.mark();
     UOI_HIP(hipMemcpyAsync(lam, o->lambdas, sizeof(double) * q, hipMemcpyHostToDevice, s));
     launch_var_boot_rows(s, o->seed, B1, N, L, rows);
-    launch_gram_f64(s, B1, N, rows, nullptr, p, Xd, p, pe, Yd, p, G, C);
+    {
+        KernelTimer kt(s, timing && diag ? &diag->kstat[UOI_KSTAT_GRAM] : nullptr);
+        launch_gram_f64(s, B1, N, rows, nullptr, p, Xd, p, pe, Yd, p, G, C);
+        kt.done((double)B1 * ((double)N * (p + pe) * 8 + (double)p * (p + pe) * 8),
+                (double)B1 * ((double)N * p * (p + 1) + 2.0 * N * p * pe));
+    }
     tm.mark();
     P.G = G;
     P.C = C;
     P.lam = lam;
-    AdmmOut out{z, u, diag && diag->iters ? diag->iters : its, diag && diag->kkt ? diag->kkt : kkt, 0, 0};
+    AdmmOut out{z, u, diag && diag->iters ? diag->iters : its, diag && diag->kkt ? diag->kkt : kkt, 0, 0,
+                timing && diag ? diag->kstat : nullptr};
     admm_solve(s, P, o->precision, o->solver, admm_w, false, out, timing ? sm + 1 : nullptr);
     tm.mark();
     launch_support_and(s, B1, p, R, z, supp_out);
@@ -397,7 +439,7 @@ static int solve_batch(int nb, int p, const double *G, const double *c, const uo
         if (u0) transpose(s, nb, p, R, u0, u, false);
         else UOI_HIP(hipMemsetAsync(u, 0, sizeof(double) * nst, s));
     }
-    AdmmOut out{z, u, iters ? iters : its, kkt ? kkt : kk, 0, 0};
+    AdmmOut out{z, u, iters ? iters : its, kkt ? kkt : kk, 0, 0, nullptr};
     admm_solve(s, P, o->precision, o->solver, w, warm, out, nullptr);
     transpose(s, nb, p, R, z, z_out, true);
     if (u_out) transpose(s, nb, p, R, u, u_out, true);

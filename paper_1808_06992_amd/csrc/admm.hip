@@ -17,7 +17,9 @@
 // tolerance is frozen (its z is the verified iterate) and a tile whose solves
 // are all frozen skips its work.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "common.hpp"
 
@@ -239,6 +241,7 @@ __global__ void k_freeze(int nb, int R, int pe, const double *__restrict__ vmax,
                          const double *__restrict__ cn, double tol, double park_tol, int it,
                          uint8_t *__restrict__ state, int32_t *__restrict__ iters,
                          double *__restrict__ kkt, int *__restrict__ active) {
+    // active[0] = all solves still active, active[1 + b] = those of bootstrap b
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     bool act = false;
     if (s < nb * R) {
@@ -254,6 +257,7 @@ __global__ void k_freeze(int nb, int R, int pe, const double *__restrict__ vmax,
                 state[s] = 2;
             } else {
                 act = true;
+                atomicAdd(&active[1 + b], 1);
             }
         }
     }
@@ -438,7 +442,7 @@ AdmmWork carve(const AdmmProblem &P, int precision, int solver, Arena &ar) {
     w.cn = ar.take<double>((size_t)P.nb * P.pe);
     w.vmax = ar.take<double>((size_t)P.nb * P.R);
     w.state = ar.take<uint8_t>((size_t)P.nb * P.R);
-    w.active = ar.take<int>(1);
+    w.active = ar.take<int>(1 + P.nb);
     if (solver == UOI_SOLVER_BATCHED) {
         w.v0 = ar.take<double>(nst);
         w.v1 = ar.take<double>(nst);
@@ -465,9 +469,9 @@ size_t admm_work_bytes(const AdmmProblem &P, int precision, int solver) {
 // number of solves still active.
 template <typename T>
 static int check(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T *z, bool only_active,
-                 double park_tol, int it, AdmmOut &out) {
+                 double park_tol, int it, AdmmOut &out, std::vector<int> &act_b) {
     UOI_HIP(hipMemsetAsync(w.vmax, 0, sizeof(double) * (size_t)P.nb * P.R, s));
-    UOI_HIP(hipMemsetAsync(w.active, 0, sizeof(int), s));
+    UOI_HIP(hipMemsetAsync(w.active, 0, sizeof(int) * (1 + P.nb), s));
     if (std::is_same<T, double>::value) {
         UOI_DISPATCH_FN(P.R, {
             KktEpi<double, 1, FN> epi{P.C, (const double *)z, w.state, P.lam, w.vmax, P.p, P.R, P.pe,
@@ -489,18 +493,40 @@ static int check(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T
     hipLaunchKernelGGL(k_freeze, dim3(cdiv(ns, 256)), dim3(256), 0, s, P.nb, P.R, P.pe, w.vmax, w.cn,
                        P.tol, park_tol, it, w.state, out.iters, out.kkt, w.active);
     UOI_LAUNCH_CHECK();
-    int active = 0;
-    UOI_HIP(hipMemcpyAsync(&active, w.active, sizeof(int), hipMemcpyDeviceToHost, s));
+    act_b.resize(1 + P.nb);
+    UOI_HIP(hipMemcpyAsync(act_b.data(), w.active, sizeof(int) * (1 + P.nb), hipMemcpyDeviceToHost, s));
     UOI_HIP(hipStreamSynchronize(s));
-    return active;
+    return act_b[0];
 }
 
 template <typename T>
 static int sweep(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T *M, const T *h,
                  T *z, T *u, T *va, T *vb, int &it, int it_cap, double park_tol, AdmmOut &out) {
-    int active = check<T>(s, P, w, z, true, park_tol, it, out);
+    std::vector<int> act_b;
+    int active = check<T>(s, P, w, z, true, park_tol, it, out, act_b);
+    uoi_kstat *ks = out.kstat ? &out.kstat[std::is_same<T, double>::value ? UOI_KSTAT_ADMM64
+                                                                           : UOI_KSTAT_ADMM32]
+                              : nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (ks) {
+        UOI_HIP(hipEventCreate(&e0));
+        UOI_HIP(hipEventCreate(&e1));
+    }
     while (active > 0 && it < it_cap) {
         int n = std::min(P.check_every, it_cap - it);
+        if (ks) {
+            // algorithmic traffic and work of one launch with the current active set
+            double by = 0.0, fl = 0.0;
+            for (int b = 0; b < P.nb; ++b)
+                if (act_b[1 + b] > 0) {
+                    by += (double)P.p * P.p * sizeof(T) + 4.0 * P.p * sizeof(T) * act_b[1 + b];
+                    fl += 2.0 * P.p * P.p * act_b[1 + b];
+                }
+            ks->bytes += by * n;
+            ks->flops += fl * n;
+            ks->launches += n;
+            UOI_HIP(hipEventRecord(e0, s));
+        }
         for (int t = 0; t < n; ++t) {
             T *vin = (it & 1) ? vb : va;
             T *vout = (it & 1) ? va : vb;
@@ -511,7 +537,17 @@ static int sweep(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T
             });
             ++it;
         }
-        active = check<T>(s, P, w, z, true, park_tol, it, out);
+        if (ks) UOI_HIP(hipEventRecord(e1, s));
+        active = check<T>(s, P, w, z, true, park_tol, it, out, act_b);
+        if (ks) {
+            float ms = 0.f;
+            UOI_HIP(hipEventElapsedTime(&ms, e0, e1));
+            ks->ms += ms;
+        }
+    }
+    if (ks) {
+        UOI_HIP(hipEventDestroy(e0));
+        UOI_HIP(hipEventDestroy(e1));
     }
     return active;
 }
@@ -551,10 +587,36 @@ void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, 
     if (solver == UOI_SOLVER_PLAIN) {
         size_t lds = sizeof(double) * 3 * (size_t)P.p;
         UOI_REQUIRE(P.p <= 256 * PLAIN_MAX_ROWS && lds <= 160 * 1024, "plain solver: p too large");
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (out.kstat) {
+            UOI_HIP(hipEventCreate(&e0));
+            UOI_HIP(hipEventCreate(&e1));
+            UOI_HIP(hipEventRecord(e0, s));
+        }
         hipLaunchKernelGGL(k_admm_plain, dim3(ns), dim3(256), lds, s, P.p, P.pe, P.R, w.M, w.h, P.G,
                            P.C, P.lam, w.cn, P.rho, P.tol, P.max_iter, P.check_every, out.z, out.u,
                            out.iters, out.kkt);
         UOI_LAUNCH_CHECK();
+        if (out.kstat) {
+            UOI_HIP(hipEventRecord(e1, s));
+            UOI_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            UOI_HIP(hipEventElapsedTime(&ms, e0, e1));
+            UOI_HIP(hipEventDestroy(e0));
+            UOI_HIP(hipEventDestroy(e1));
+            std::vector<int32_t> its(ns);
+            UOI_HIP(hipMemcpy(its.data(), out.iters, sizeof(int32_t) * ns, hipMemcpyDeviceToHost));
+            uoi_kstat &k = out.kstat[UOI_KSTAT_PLAIN];
+            double pp = (double)P.p * P.p;
+            for (int v : its) {
+                double n = v < 0 ? P.max_iter : v;
+                double checks = std::floor(n / P.check_every) + 1.0;
+                k.bytes += (n + checks) * pp * sizeof(double);
+                k.flops += (n + checks) * 2.0 * pp;
+            }
+            k.ms += ms;
+            k.launches += 1;
+        }
     } else if (precision == UOI_FP64) {
         hipLaunchKernelGGL(k_refresh_v<double>, dim3(cdiv(nst, 256)), dim3(256), 0, s, nst, out.z,
                            out.u, w.v0, w.v1);

@@ -187,6 +187,7 @@ struct AdmmOut {
     double *kkt;         // [nb*R]
     int64_t unconverged;
     int max_iters;
+    uoi_kstat *kstat;    // [UOI_KSTAT_N] accumulated when non-null (timing runs)
 };
 
 size_t admm_work_bytes(const AdmmProblem &P, int precision, int solver);
