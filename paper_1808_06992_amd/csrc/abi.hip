@@ -269,8 +269,7 @@ static int lasso_fit(int n, int p, const double *X, const double *y, const uoi_o
     launch_split(s, o->seed, TAG_LASSO_SPLIT, B2, n, ntr, flag);
     launch_compact_rows(s, B2, n, flag, ntr, tr, ev);
     launch_gram_f64(s, B2, ntr, tr, nullptr, p, X, p, 1, y, 1, GT, CT);
-    launch_gram_f64(s, B2, nev, ev, nullptr, p, X, p, 1, y, 1, GE, CE);
-    launch_colsq(s, B2, nev, ev, nullptr, 1, y, 1, sE);
+    launch_gram_f64(s, B2, nev, ev, nullptr, p, X, p, 1, y, 1, GE, CE, sE);
     tm.mark();
     E.GT = GT; E.CT = CT; E.GE = GE; E.CE = CE; E.sE = sE;
     estimate(s, E, est_w, beta_out, jstar_out, diag ? diag->losses : nullptr, timing ? sm + 6 : nullptr);

@@ -21,90 +21,10 @@
 #include <cstring>
 #include <type_traits>
 
+#include "bgemm.hpp"
 #include "common.hpp"
 
 namespace uoi {
-
-// ---------------------------------------------------------------------------
-// Batched product Y_b = A_b V_b, A_b symmetric p x p, V_b p x R (row-major).
-// Workgroup = 4 waves stacked along rows; a wave owns a (16 FM) x (16 FN) block
-// of the output as FM x FN MFMA 16x16x4 accumulators.  Because A is symmetric,
-// the MFMA operand A[i][k] is read as A[k][i]: 16 consecutive doubles of a row.
-// ---------------------------------------------------------------------------
-template <typename T, int FM, int FN>
-struct Tile {
-    typedef typename std::conditional<std::is_same<T, double>::value, dx4, fx4>::type acc_t;
-    acc_t acc[FM][FN];
-};
-
-template <typename T, int FM, int FN, class Epi>
-__global__ __launch_bounds__(256) void k_bgemm(int p, int R, const T *__restrict__ A,
-                                               const T *__restrict__ V, Epi epi) {
-    typedef typename Tile<T, FM, FN>::acc_t acc_t;
-    const int b = blockIdx.z;
-    const int r0 = blockIdx.x * (16 * FN);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int i_base = blockIdx.y * (64 * FM) + wid * (16 * FM);
-    const int lr = lane & 15, lk = lane >> 4;
-    if (!epi.tile_active(b, r0, 16 * FN)) return;
-    if (i_base >= p) return;  // whole wave below the matrix (no shared memory used)
-
-    const T *Ab = A + (size_t)b * p * p;
-    const T *Vb = V + (size_t)b * p * R;
-    acc_t acc[FM][FN];
-#pragma unroll
-    for (int a = 0; a < FM; ++a)
-#pragma unroll
-        for (int c = 0; c < FN; ++c)
-            for (int t = 0; t < 4; ++t) acc[a][c][t] = 0;
-
-    int icol[FM], rcol[FN];
-    bool iok[FM], rok[FN];
-#pragma unroll
-    for (int a = 0; a < FM; ++a) {
-        icol[a] = i_base + 16 * a + lr;
-        iok[a] = icol[a] < p;
-    }
-#pragma unroll
-    for (int c = 0; c < FN; ++c) {
-        rcol[c] = r0 + 16 * c + lr;
-        rok[c] = rcol[c] < R;
-    }
-
-    const int pk = p & ~15;  // main loop: 16 rows of k per trip, 4 MFMA K-steps
-    for (int k0 = 0; k0 < pk; k0 += 16) {
-        T av[4][FM], bv[4][FN];
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int k = k0 + 4 * s + lk;
-#pragma unroll
-            for (int a = 0; a < FM; ++a) av[s][a] = iok[a] ? Ab[(size_t)k * p + icol[a]] : T(0);
-#pragma unroll
-            for (int c = 0; c < FN; ++c) bv[s][c] = rok[c] ? Vb[(size_t)k * R + rcol[c]] : T(0);
-        }
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-#pragma unroll
-            for (int a = 0; a < FM; ++a)
-#pragma unroll
-                for (int c = 0; c < FN; ++c) acc[a][c] = mfma16x16x4(av[s][a], bv[s][c], acc[a][c]);
-    }
-    for (int k0 = pk; k0 < p; k0 += 4) {  // ragged tail
-        const int k = k0 + lk;
-        const bool kok = k < p;
-#pragma unroll
-        for (int a = 0; a < FM; ++a) {
-            T av = (kok && iok[a]) ? Ab[(size_t)k * p + icol[a]] : T(0);
-#pragma unroll
-            for (int c = 0; c < FN; ++c) {
-                T bv = (kok && rok[c]) ? Vb[(size_t)k * R + rcol[c]] : T(0);
-                acc[a][c] = mfma16x16x4(av, bv, acc[a][c]);
-            }
-        }
-    }
-    // element (i, r) of the block: i = i_base + 16a + mfma_row(lk, t), r = r0 + 16c + lr
-    epi.apply(b, i_base, r0, lr, lk, acc);
-}
 
 // --- epilogue: plain store --------------------------------------------------
 template <typename T, int FM, int FN>
@@ -393,22 +313,6 @@ __global__ __launch_bounds__(256) void k_admm_plain(int p, int pe, int R, const 
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
-template <typename T, int FM, int FN, class Epi>
-static void run_bgemm(hipStream_t s, int nb, int p, int R, const T *A, const T *V, const Epi &epi) {
-    dim3 grid(cdiv(R, 16 * FN), cdiv(p, 64 * FM), nb);
-    hipLaunchKernelGGL((k_bgemm<T, FM, FN, Epi>), grid, dim3(256), 0, s, p, R, A, V, epi);
-    UOI_LAUNCH_CHECK();
-}
-
-// Column-block width: the smallest 16-multiple that covers R up to 64.
-#define UOI_DISPATCH_FN(R, ...)                                   \
-    do {                                                          \
-        if ((R) <= 16) { constexpr int FN = 1; __VA_ARGS__; }      \
-        else if ((R) <= 32) { constexpr int FN = 2; __VA_ARGS__; } \
-        else if ((R) <= 48) { constexpr int FN = 3; __VA_ARGS__; } \
-        else { constexpr int FN = 4; __VA_ARGS__; }                \
-    } while (0)
-
 void launch_matmul_f64(hipStream_t s, int nb, int p, int R, const double *A, const double *V,
                        double *Y) {
     UOI_DISPATCH_FN(R, {

@@ -147,10 +147,11 @@ void launch_expand_blocks(hipStream_t s, int nb, int nblk, int N, int L, const u
                           int32_t *train, int32_t *eval, int32_t *ntr, int32_t *nev);
 
 // Gram: G[b] = X_r'X_r/m (full symmetric storage), C[b] = X_r'Y_r/m; per-batch row
-// counts may be given (mcount != nullptr) with row lists at stride m.
+// counts may be given (mcount != nullptr) with row lists at stride m.  When pe < 32
+// and ss != nullptr, ss[b][e] = sum_r Y[r][e]^2 / m comes out of the same product.
 void launch_gram_f64(hipStream_t s, int nb, int m, const int32_t *rows, const int32_t *mcount,
                      int p, const double *X, int ldx, int pe, const double *Y, int ldy,
-                     double *G, double *C);
+                     double *G, double *C, double *ss = nullptr);
 // sum of squares of Y columns over sampled rows / m:  ss[b*pe + e]
 void launch_colsq(hipStream_t s, int nb, int m, const int32_t *rows, const int32_t *mcount,
                   int pe, const double *Y, int ldy, double *ss);

@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <vector>
 
+#include "bgemm.hpp"
 #include "common.hpp"
 
 namespace uoi {
@@ -196,39 +197,6 @@ struct CgEpi {
         apply_impl<Acc, FM, FN>(b, i_base, r0, lr, lk, acc);
     }
 };
-
-// The product kernel of admm.hip is instantiated here through a thin copy of its
-// launch (the kernel template lives in that translation unit); CG uses its own
-// simple MFMA product with the same tiling.
-template <int FN>
-__global__ __launch_bounds__(256) void k_cg_matvec(int p, int nL, const double *__restrict__ A,
-                                                   const double *__restrict__ V, CgEpi epi) {
-    const int b = blockIdx.z;
-    const int r0 = blockIdx.x * (16 * FN);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int i_base = blockIdx.y * 64 + wid * 16;
-    const int lr = lane & 15, lk = lane >> 4;
-    if (!epi.tile_active(b, r0, 16 * FN)) return;
-    if (i_base >= p) return;
-    const double *Ab = A + (size_t)b * p * p;
-    const double *Vb = V + (size_t)b * p * nL;
-    dx4 acc[1][FN];
-    for (int c = 0; c < FN; ++c) acc[0][c] = dx4{0, 0, 0, 0};
-    const int icol = i_base + lr;
-    const bool iok = icol < p;
-    for (int k0 = 0; k0 < p; k0 += 4) {
-        const int k = k0 + lk;
-        const bool kok = k < p;
-        double av = (kok && iok) ? Ab[(size_t)k * p + icol] : 0.0;
-#pragma unroll
-        for (int c = 0; c < FN; ++c) {
-            int r = r0 + 16 * c + lr;
-            double bv = (kok && r < nL) ? Vb[(size_t)k * nL + r] : 0.0;
-            acc[0][c] = mfma16x16x4(av, bv, acc[0][c]);
-        }
-    }
-    epi.apply<dx4, 1, FN>(b, i_base, r0, lr, lk, acc);
-}
 
 __global__ void k_cg_init(int nb, int p, int pe, int nL, int W, const uint64_t *__restrict__ supp,
                           const int32_t *__restrict__ Lidx, const double *__restrict__ CT,
@@ -457,15 +425,7 @@ void estimate(hipStream_t s, const EstimProblem &E, void *work, double *beta_out
         UOI_LAUNCH_CHECK();
         CgEpi epi{E.supp, w.Lidx, w.state, w.P, w.AP, w.pAp, E.p, nL, W};
         for (int it = 0; it < kCgMaxIter; ++it) {
-            if (nL <= 16)
-                hipLaunchKernelGGL(k_cg_matvec<1>, dim3(cdiv(nL, 16), cdiv(E.p, 64), E.nb), dim3(256), 0,
-                                   s, E.p, nL, E.GT, w.P, epi);
-            else if (nL <= 32)
-                hipLaunchKernelGGL(k_cg_matvec<2>, dim3(cdiv(nL, 32), cdiv(E.p, 64), E.nb), dim3(256), 0,
-                                   s, E.p, nL, E.GT, w.P, epi);
-            else
-                hipLaunchKernelGGL(k_cg_matvec<4>, dim3(cdiv(nL, 64), cdiv(E.p, 64), E.nb), dim3(256), 0,
-                                   s, E.p, nL, E.GT, w.P, epi);
+            UOI_DISPATCH_FN(nL, run_bgemm<double, 1, FN>(s, E.nb, E.p, nL, E.GT, w.P, epi));
             hipLaunchKernelGGL(k_cg_update, eg, dim3(256), 0, s, E.p, nL, w.state, w.rr, w.pAp, w.P, w.AP,
                                w.X, w.Rv, w.rrn);
             hipLaunchKernelGGL(k_cg_dir, eg, dim3(256), 0, s, E.p, nL, w.state, w.rr, w.rrn, w.Rv, w.P);

@@ -5,30 +5,55 @@
 // resampled copy of X is ever written.  The product dominates the paper's
 // single-node profile (its matrix multiplication inside LASSO-ADMM, Sec. IV-A.1).
 //
-// Work decomposition: 64x64 output tiles; G is symmetric, so only tiles on or
-// below the diagonal are computed and each is written to both halves.  A tile
-// streams the sampled rows in chunks of 16 through LDS; 4 waves each own a
-// 32x32 quadrant as 2x2 MFMA 16x16x4 blocks.
+// Columns: the design X (p columns) followed, when the response has fewer than
+// 32 columns (the LASSO's y), by the response itself ("augmented" columns), so
+// one symmetric product yields G, C = X'y/m and the mean squares y'y/m.  Many
+// response columns (VAR) get their own rectangular tiles instead.
+//
+// Work decomposition: 128x128 output tiles of the lower triangle (plus C
+// tiles).  A tile streams the sampled rows in chunks of 16 through LDS: the
+// next chunk's gathered values are loaded into registers while the current
+// chunk is multiplied, and the row indices two chunks ahead, so the index ->
+// value dependency never stalls the MFMAs.  4 waves each own a 64x64 quadrant
+// as 4x4 MFMA 16x16x4 blocks.  The upper triangle is filled afterwards by a
+// coalesced transpose.
 #include "common.hpp"
 
 namespace uoi {
 
 namespace {
-constexpr int GT = 64;   // tile edge
+constexpr int GT = 128;  // tile edge
 constexpr int GK = 16;   // rows per LDS chunk
+constexpr int AUG_MAX = 32;  // response columns folded into the symmetric product
 }
 
-__global__ __launch_bounds__(256) void k_gram_f64(int m, const int32_t *__restrict__ rows,
-                                                  const int32_t *__restrict__ mcount, int p,
-                                                  const double *__restrict__ X, int ldx, int pe,
-                                                  const double *__restrict__ Y, int ldy,
-                                                  double *__restrict__ G, double *__restrict__ C,
-                                                  int T, int Tc) {
+struct GramArgs {
+    int m;
+    const int32_t *rows;
+    const int32_t *mcount;
+    int p, pa;        // design columns, augmented response columns (0..AUG_MAX-1)
+    const double *X;
+    int ldx;
+    int pe;           // response columns handled by C tiles (0 when augmented)
+    const double *Y;
+    int ldy;
+    double *G, *C, *ss;  // ss: mean squares of the augmented responses (nullable)
+    int T, Tc;
+};
+
+// value of augmented column j of sampled row r
+__device__ __forceinline__ double aug_col(const GramArgs &g, size_t r, int j) {
+    if (j < g.p) return g.X[r * g.ldx + j];
+    if (j < g.p + g.pa) return g.Y[r * g.ldy + (j - g.p)];
+    return 0.0;
+}
+
+__global__ __launch_bounds__(256, 2) void k_gram_f64(GramArgs g) {
     __shared__ double As[GK][GT];
     __shared__ double Bs[GK][GT];
     const int b = blockIdx.y;
     int tile = blockIdx.x;
-    const int ntri = T * (T + 1) / 2;
+    const int ntri = g.T * (g.T + 1) / 2;
     int ti, tj;
     bool isC;
     if (tile < ntri) {
@@ -40,69 +65,132 @@ __global__ __launch_bounds__(256) void k_gram_f64(int m, const int32_t *__restri
         isC = false;
     } else {
         tile -= ntri;
-        ti = tile / Tc;
-        tj = tile % Tc;
+        ti = tile / g.Tc;
+        tj = tile % g.Tc;
         isC = true;
     }
     const int i0 = ti * GT, j0 = tj * GT;
-    const int mb = mcount ? mcount[b] : m;
-    const int32_t *rb = rows + (size_t)b * m;
-    const double *Bsrc = isC ? Y : X;
-    const int ldb = isC ? ldy : ldx;
-    const int nb_cols = isC ? pe : p;
+    const int mb = g.mcount ? g.mcount[b] : g.m;
+    const int32_t *rb = g.rows + (size_t)b * g.m;
+    const int naug = g.p + g.pa;
 
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wid = tid >> 6;
     const int wm = wid >> 1, wn = wid & 1;
     const int lr = lane & 15, lk = lane >> 4;
+    // this thread stages rows kk = (tid >> 7) + 2q, column cc = tid & 127
+    const int kk0 = tid >> 7, cc = tid & 127;
+    const int ia = i0 + cc, jb = j0 + cc;
 
-    dx4 acc[2][2];
-    for (int a = 0; a < 2; ++a)
-        for (int c = 0; c < 2; ++c) acc[a][c] = dx4{0, 0, 0, 0};
-
-    for (int k0 = 0; k0 < mb; k0 += GK) {
-        // stage 16 gathered rows: columns [i0, i0+64) of X and [j0, j0+64) of X or Y
+    dx4 acc[4][4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            int e = threadIdx.x + 256 * t;
-            int kk = e >> 6, cc = e & 63;
-            double va = 0.0, vb = 0.0;
-            if (k0 + kk < mb) {
-                size_t r = (size_t)rb[k0 + kk];
-                if (i0 + cc < p) va = X[r * ldx + i0 + cc];
-                if (j0 + cc < nb_cols) vb = Bsrc[r * ldb + j0 + cc];
-            }
-            As[kk][cc] = va;
-            Bs[kk][cc] = vb;
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = dx4{0, 0, 0, 0};
+
+    int idx1[8], idx2[8];
+    double ra[8], rbv[8];
+    auto load_idx = [&](int k0, int (&idx)[8]) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            int k = k0 + kk0 + 2 * q;
+            idx[q] = k < mb ? rb[k] : -1;
         }
-        __syncthreads();
+    };
+    auto load_val = [&](const int (&idx)[8]) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            double va = 0.0, vb = 0.0;
+            if (idx[q] >= 0) {
+                size_t r = (size_t)idx[q];
+                va = ia < naug ? aug_col(g, r, ia) : 0.0;
+                if (isC) vb = jb < g.pe ? g.Y[r * g.ldy + jb] : 0.0;
+                else vb = jb < naug ? aug_col(g, r, jb) : 0.0;
+            }
+            ra[q] = va;
+            rbv[q] = vb;
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            As[kk0 + 2 * q][cc] = ra[q];
+            Bs[kk0 + 2 * q][cc] = rbv[q];
+        }
+    };
+
+    const int nchunk = (mb + GK - 1) / GK;
+    load_idx(0, idx1);
+    load_val(idx1);
+    load_idx(GK, idx1);
+    store();
+    __syncthreads();
+    for (int c = 0; c < nchunk; ++c) {
+        const bool more = c + 1 < nchunk;
+        if (more) {
+            load_val(idx1);                      // values of chunk c+1
+            load_idx((c + 2) * GK, idx2);        // indices of chunk c+2
+        }
 #pragma unroll
         for (int s = 0; s < GK / 4; ++s) {
-            double a0 = As[4 * s + lk][wm * 32 + lr];
-            double a1 = As[4 * s + lk][wm * 32 + 16 + lr];
-            double b0 = Bs[4 * s + lk][wn * 32 + lr];
-            double b1 = Bs[4 * s + lk][wn * 32 + 16 + lr];
-            acc[0][0] = mfma16x16x4(a0, b0, acc[0][0]);
-            acc[0][1] = mfma16x16x4(a0, b1, acc[0][1]);
-            acc[1][0] = mfma16x16x4(a1, b0, acc[1][0]);
-            acc[1][1] = mfma16x16x4(a1, b1, acc[1][1]);
+            double av[4], bv[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) av[a] = As[4 * s + lk][wm * 64 + 16 * a + lr];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) bv[a] = Bs[4 * s + lk][wn * 64 + 16 * a + lr];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[a][q] = mfma16x16x4(av[a], bv[q], acc[a][q]);
+        }
+        __syncthreads();
+        if (more) {
+            store();
+#pragma unroll
+            for (int q = 0; q < 8; ++q) idx1[q] = idx2[q];
         }
         __syncthreads();
     }
 
     const double inv = 1.0 / (double)mb;
-    for (int fm = 0; fm < 2; ++fm)
-        for (int fn = 0; fn < 2; ++fn)
+    const size_t gb = (size_t)b * g.p;
+#pragma unroll
+    for (int fm = 0; fm < 4; ++fm)
+#pragma unroll
+        for (int fn = 0; fn < 4; ++fn)
+#pragma unroll
             for (int t = 0; t < 4; ++t) {
-                int i = i0 + wm * 32 + fm * 16 + mfma_row(0.0, lk, t);
-                int j = j0 + wn * 32 + fn * 16 + lr;
-                double v = acc[fm][fn][t] * inv;
+                const int i = i0 + wm * 64 + fm * 16 + mfma_row(0.0, lk, t);
+                const int j = j0 + wn * 64 + fn * 16 + lr;
+                const double v = acc[fm][fn][t] * inv;
                 if (isC) {
-                    if (i < p && j < pe) C[((size_t)b * p + i) * pe + j] = v;
-                } else if (i < p && j < p) {
-                    G[((size_t)b * p + i) * p + j] = v;
-                    G[((size_t)b * p + j) * p + i] = v;
+                    if (i < g.p && j < g.pe) g.C[(gb + i) * g.pe + j] = v;
+                } else if (j <= i && i < naug) {
+                    if (i < g.p) g.G[(gb + i) * g.p + j] = v;        // design block (lower)
+                    else if (j < g.p) g.C[(gb + j) * g.pa + (i - g.p)] = v;  // X'y block
+                    else if (i == j && g.ss) g.ss[(size_t)b * g.pa + (i - g.p)] = v;  // y'y diagonal
                 }
             }
+}
+
+// Upper triangle from the lower one: G[j][i] = G[i][j] for i > j, by 32x32
+// tiles transposed through LDS (coalesced reads and writes).
+__global__ void k_symmetrize(int p, double *__restrict__ G) {
+    __shared__ double t[32][33];
+    const int b = blockIdx.z;
+    const int bi = blockIdx.y, bj = blockIdx.x;  // source tile rows bi, columns bj, bi >= bj
+    if (bj > bi) return;
+    double *Gb = G + (size_t)b * p * p;
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    for (int r = ty; r < 32; r += 8) {
+        int i = bi * 32 + r, j = bj * 32 + tx;
+        if (i < p && j < p) t[r][tx] = Gb[(size_t)i * p + j];
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        int i = bj * 32 + r, j = bi * 32 + tx;  // destination (i, j) = source (j, i)
+        if (i < p && j < p && j > i) Gb[(size_t)i * p + j] = t[tx][r];
+    }
 }
 
 // ss[b][e] = sum over sampled rows of Y[r][e]^2 / m
@@ -133,12 +221,20 @@ __global__ __launch_bounds__(256) void k_colsq(int m, const int32_t *__restrict_
 
 void launch_gram_f64(hipStream_t s, int nb, int m, const int32_t *rows, const int32_t *mcount,
                      int p, const double *X, int ldx, int pe, const double *Y, int ldy,
-                     double *G, double *C) {
-    int T = (int)cdiv(p, GT);
-    int Tc = (C != nullptr && pe > 0) ? (int)cdiv(pe, GT) : 0;
-    int tiles = T * (T + 1) / 2 + T * Tc;
-    hipLaunchKernelGGL(k_gram_f64, dim3(tiles, nb), dim3(256), 0, s, m, rows, mcount, p, X, ldx,
-                       pe, Y, ldy, G, C, T, Tc);
+                     double *G, double *C, double *ss) {
+    GramArgs g{};
+    g.m = m; g.rows = rows; g.mcount = mcount; g.p = p; g.X = X; g.ldx = ldx;
+    g.Y = Y; g.ldy = ldy; g.G = G; g.C = C; g.ss = ss;
+    const bool aug = C != nullptr && pe > 0 && pe < AUG_MAX;
+    g.pa = aug ? pe : 0;
+    g.pe = (C != nullptr && !aug) ? pe : 0;
+    g.T = (int)cdiv(p + g.pa, GT);
+    g.Tc = g.pe > 0 ? (int)cdiv(g.pe, GT) : 0;
+    const int tiles = g.T * (g.T + 1) / 2 + (int)cdiv(p, GT) * g.Tc;
+    hipLaunchKernelGGL(k_gram_f64, dim3(tiles, nb), dim3(256), 0, s, g);
+    UOI_LAUNCH_CHECK();
+    const int T32 = (int)cdiv(p, 32);
+    hipLaunchKernelGGL(k_symmetrize, dim3(T32, T32, nb), dim3(32, 8), 0, s, p, G);
     UOI_LAUNCH_CHECK();
 }
 

@@ -10,9 +10,10 @@
 // and sweeping every block leaves -A^{-1}.  Pivots are Schur complements of
 // an SPD matrix, so no pivoting is needed.
 //
-// Per block step: (1) one workgroup per matrix sweeps the kb x kb pivot block
-// in LDS; (2) a row-parallel kernel forms W = A_:K Q and keeps the old panel
-// A_:K; (3) a tiled MFMA kernel applies the rank-kb update to the whole matrix.
+// Per block step: (1) one workgroup per matrix sweeps the kb x kb pivot block in
+// LDS (Q = A_KK^{-1}); (2) a row-parallel MFMA kernel forms W = A_:K Q and keeps
+// the old panel A_:K; (3) a tiled MFMA kernel applies the rank-kb update to the
+// whole matrix.
 #include "common.hpp"
 
 namespace uoi {
@@ -23,14 +24,18 @@ constexpr int SMALL = 88;  // whole-matrix in-LDS sweep up to this size (LDS <= 
 }
 
 // Unblocked symmetric sweep of an n x n matrix held in LDS (row stride ld).
-// Leaves -A^{-1} in place.
+// Leaves -A^{-1} in place.  256 threads; thread (ty, tx) = (tid/16, tid%16)
+// owns rows ty + 16a and columns tx + 16c.
 __device__ void lds_sweep(double *A, int n, int ld) {
+    const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
     for (int k = 0; k < n; ++k) {
         const double pinv = 1.0 / A[k * ld + k];
         // update the off-pivot part first: it reads row/column k only
-        for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-            int i = e / n, j = e % n;
-            if (i != k && j != k) A[i * ld + j] -= A[i * ld + k] * A[k * ld + j] * pinv;
+        for (int i = ty; i < n; i += 16) {
+            if (i == k) continue;
+            const double aik = A[i * ld + k] * pinv;
+            for (int j = tx; j < n; j += 16)
+                if (j != k) A[i * ld + j] -= aik * A[k * ld + j];
         }
         __syncthreads();
         for (int i = threadIdx.x; i < n; i += blockDim.x)
@@ -76,70 +81,44 @@ __global__ void k_negate(size_t n, double *__restrict__ M) {
     if (e < n) M[e] = -M[e];
 }
 
-// (1) Q = A_KK^{-1} (stored as +Q) for pivot block [k0, k0+kb).
+// (1) Q = A_KK^{-1} for pivot block [k0, k0+kb) (one workgroup per matrix).
 __global__ __launch_bounds__(256) void k_pivot(int p, int k0, int kb, const double *__restrict__ A,
                                                double *__restrict__ Q) {
-    __shared__ double S[NB * NB];
+    constexpr int LD = NB + 1;
+    __shared__ double S[NB * LD];
     const int b = blockIdx.x;
     const double *Ab = A + (size_t)b * p * p;
-    for (int e = threadIdx.x; e < kb * kb; e += 256) {
-        int i = e / kb, j = e % kb;
-        S[i * kb + j] = Ab[(size_t)(k0 + i) * p + k0 + j];
+    for (int e = threadIdx.x; e < NB * NB; e += 256) {
+        int i = e / NB, j = e % NB;
+        if (i < kb && j < kb) S[i * LD + j] = Ab[(size_t)(k0 + i) * p + k0 + j];
     }
     __syncthreads();
-    lds_sweep(S, kb, kb);
+    lds_sweep(S, kb, LD);  // S = -Q
     double *Qb = Q + (size_t)b * NB * NB;
-    for (int e = threadIdx.x; e < kb * kb; e += 256) Qb[e] = -S[e];
+    for (int e = threadIdx.x; e < NB * NB; e += 256) {
+        int i = e / NB, j = e % NB;
+        Qb[e] = (i < kb && j < kb) ? -S[i * LD + j] : 0.0;  // stored NB x NB, zero padded
+    }
 }
 
-// (2) W[i] = A[i, K] Q and Old[i] = A[i, K] for every row i (row-major, width NB).
+// (2) Panel for rows [i0, i0+64): Old = A[i, K], W = A[i, K] Q on MFMA.
 __global__ __launch_bounds__(256) void k_panel(int p, int k0, int kb, const double *__restrict__ A,
                                                const double *__restrict__ Q, double *__restrict__ W,
                                                double *__restrict__ Old) {
-    __shared__ double Qs[NB * NB];
+    constexpr int LD = 64 + 1;
+    __shared__ double As[NB * LD];  // As[t][r] = A[i0 + r][k0 + t]
+    __shared__ double Qs[NB * LD];  // Qs[t][c] = Q[t][c]
     const int b = blockIdx.y;
+    const int i0 = blockIdx.x * 64;
+    const double *Ab = A + (size_t)b * p * p;
     const double *Qb = Q + (size_t)b * NB * NB;
-    for (int e = threadIdx.x; e < kb * kb; e += 256) Qs[e] = Qb[e];
-    __syncthreads();
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= p) return;
-    const double *row = A + ((size_t)b * p + i) * p + k0;
-    double *Wr = W + ((size_t)b * p + i) * NB;
-    double *Or = Old + ((size_t)b * p + i) * NB;
-    double a[NB];
-#pragma unroll
-    for (int t = 0; t < NB; ++t) {
-        a[t] = t < kb ? row[t] : 0.0;
-        Or[t] = a[t];
-    }
-    for (int j = 0; j < NB; ++j) {
-        double acc = 0.0;
-        if (j < kb) {
-#pragma unroll
-            for (int t = 0; t < NB; ++t) acc += a[t] * (t < kb ? Qs[t * kb + j] : 0.0);
-        }
-        Wr[j] = acc;
-    }
-}
-
-// (3) Rank-kb update of a 64x64 tile of A:
-//   i,j not in K: A_ij -= W_i . Old_j ;  i not in K, j in K: A_ij = W_i[j-k0]
-//   i in K, j not in K: A_ij = W_j[i-k0] ;  i, j in K: A_ij = -Q
-__global__ __launch_bounds__(256) void k_update(int p, int k0, int kb, double *__restrict__ A,
-                                                const double *__restrict__ W,
-                                                const double *__restrict__ Old,
-                                                const double *__restrict__ Q) {
-    // pivot-index-major staging: Ws[t][r] = W[i0 + r][t], Os[t][r] = Old[j0 + r][t]
-    __shared__ double Ws[NB][64];
-    __shared__ double Os[NB][64];
-    const int b = blockIdx.z;
-    const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
-    const double *Wb = W + (size_t)b * p * NB;
-    const double *Ob = Old + (size_t)b * p * NB;
+    double *Ob = Old + (size_t)b * p * NB;
     for (int e = threadIdx.x; e < 64 * NB; e += 256) {
         int r = e / NB, t = e % NB;
-        Ws[t][r] = (i0 + r < p) ? Wb[(size_t)(i0 + r) * NB + t] : 0.0;
-        Os[t][r] = (j0 + r < p) ? Ob[(size_t)(j0 + r) * NB + t] : 0.0;
+        double v = (i0 + r < p && t < kb) ? Ab[(size_t)(i0 + r) * p + k0 + t] : 0.0;
+        As[t * LD + r] = v;
+        if (i0 + r < p) Ob[(size_t)(i0 + r) * NB + t] = v;
+        Qs[r * LD + t] = Qb[e];  // (r, t) doubles as (row, column) of Q here
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -148,30 +127,90 @@ __global__ __launch_bounds__(256) void k_update(int p, int k0, int kb, double *_
     dx4 acc[2][2];
     for (int a = 0; a < 2; ++a)
         for (int c = 0; c < 2; ++c) acc[a][c] = dx4{0, 0, 0, 0};
+#pragma unroll
     for (int s = 0; s < NB / 4; ++s) {
-        double a0 = Ws[4 * s + lk][wm * 32 + lr];
-        double a1 = Ws[4 * s + lk][wm * 32 + 16 + lr];
-        double b0 = Os[4 * s + lk][wn * 32 + lr];
-        double b1 = Os[4 * s + lk][wn * 32 + 16 + lr];
+        double a0 = As[(4 * s + lk) * LD + wm * 32 + lr];
+        double a1 = As[(4 * s + lk) * LD + wm * 32 + 16 + lr];
+        double b0 = Qs[(4 * s + lk) * LD + wn * 32 + lr];
+        double b1 = Qs[(4 * s + lk) * LD + wn * 32 + 16 + lr];
         acc[0][0] = mfma16x16x4(a0, b0, acc[0][0]);
         acc[0][1] = mfma16x16x4(a0, b1, acc[0][1]);
         acc[1][0] = mfma16x16x4(a1, b0, acc[1][0]);
         acc[1][1] = mfma16x16x4(a1, b1, acc[1][1]);
     }
-    double *Ab = A + (size_t)b * p * p;
-    const double *Qb = Q + (size_t)b * NB * NB;
+    double *Wb = W + (size_t)b * p * NB;
     for (int fm = 0; fm < 2; ++fm)
         for (int fn = 0; fn < 2; ++fn)
             for (int t = 0; t < 4; ++t) {
-                int il = wm * 32 + fm * 16 + mfma_row(0.0, lk, t), jl = wn * 32 + fn * 16 + lr;
-                int i = i0 + il, j = j0 + jl;
+                int r = wm * 32 + fm * 16 + mfma_row(0.0, lk, t), c = wn * 32 + fn * 16 + lr;
+                if (i0 + r < p) Wb[(size_t)(i0 + r) * NB + c] = acc[fm][fn][t];
+            }
+}
+
+// (3) Rank-kb update of a 128x128 tile of A:
+//   i,j not in K: A_ij -= W_i . Old_j ;  i not in K, j in K: A_ij = W_i[j-k0]
+//   i in K, j not in K: A_ij = W_j[i-k0] ;  i, j in K: A_ij = -Q
+// W and Old are staged through LDS in quarters of the pivot index, transposed
+// (pivot-index-major, padded rows) so that the MFMA operand reads are conflict
+// free; each wave owns a 64x64 quadrant as 4x4 MFMA blocks.
+__global__ __launch_bounds__(256, 2) void k_update(int p, int k0, int kb, double *__restrict__ A,
+                                                   const double *__restrict__ W,
+                                                   const double *__restrict__ Old,
+                                                   const double *__restrict__ Q) {
+    constexpr int QK = 16, LD = 128 + 1;
+    __shared__ double Ws[QK * LD];
+    __shared__ double Os[QK * LD];
+    const int b = blockIdx.z;
+    const int i0 = blockIdx.y * 128, j0 = blockIdx.x * 128;
+    const double *Wb = W + (size_t)b * p * NB;
+    const double *Ob = Old + (size_t)b * p * NB;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int wm = wid >> 1, wn = wid & 1;
+    const int lr = lane & 15, lk = lane >> 4;
+    dx4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = dx4{0, 0, 0, 0};
+    const int nq = (kb + QK - 1) / QK;
+    for (int h = 0; h < nq; ++h) {
+        for (int e = threadIdx.x; e < 128 * QK; e += 256) {
+            int r = e / QK, t = e % QK;
+            Ws[t * LD + r] = (i0 + r < p) ? Wb[(size_t)(i0 + r) * NB + h * QK + t] : 0.0;
+            Os[t * LD + r] = (j0 + r < p) ? Ob[(size_t)(j0 + r) * NB + h * QK + t] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < QK / 4; ++s) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) av[a] = Ws[(4 * s + lk) * LD + wm * 64 + 16 * a + lr];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) bv[a] = Os[(4 * s + lk) * LD + wn * 64 + 16 * a + lr];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[a][c] = mfma16x16x4(av[a], bv[c], acc[a][c]);
+        }
+        __syncthreads();
+    }
+    double *Ab = A + (size_t)b * p * p;
+    const double *Qb = Q + (size_t)b * NB * NB;
+#pragma unroll
+    for (int fm = 0; fm < 4; ++fm)
+#pragma unroll
+        for (int fn = 0; fn < 4; ++fn)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int i = i0 + wm * 64 + fm * 16 + mfma_row(0.0, lk, t);
+                const int j = j0 + wn * 64 + fn * 16 + lr;
                 if (i >= p || j >= p) continue;
-                bool iK = i >= k0 && i < k0 + kb, jK = j >= k0 && j < k0 + kb;
+                const bool iK = i >= k0 && i < k0 + kb, jK = j >= k0 && j < k0 + kb;
                 double *dst = Ab + (size_t)i * p + j;
-                if (!iK && !jK) *dst -= acc[fm][fn][t];        // A_ij - A_iK Q A_Kj
-                else if (!iK) *dst = Ws[j - k0][il];             // A_iK Q
-                else if (!jK) *dst = Wb[(size_t)j * NB + (i - k0)];  // Q A_Kj = (A_jK Q)'
-                else *dst = -Qb[(i - k0) * kb + (j - k0)];       // -Q
+                if (!iK && !jK) *dst -= acc[fm][fn][t];                 // A_ij - A_iK Q A_Kj
+                else if (!iK) *dst = Wb[(size_t)i * NB + (j - k0)];      // A_iK Q
+                else if (!jK) *dst = Wb[(size_t)j * NB + (i - k0)];      // Q A_Kj = (A_jK Q)'
+                else *dst = -Qb[(i - k0) * NB + (j - k0)];               // -Q
             }
 }
 
@@ -197,8 +236,8 @@ void spd_inverse_f64(hipStream_t s, int nb, int p, const double *G, double rho, 
     for (int k0 = 0; k0 < p; k0 += NB) {
         int kb = std::min(NB, p - k0);
         hipLaunchKernelGGL(k_pivot, dim3(nb), dim3(256), 0, s, p, k0, kb, M, Q);
-        hipLaunchKernelGGL(k_panel, dim3(cdiv(p, 256), nb), dim3(256), 0, s, p, k0, kb, M, Q, W, Old);
-        hipLaunchKernelGGL(k_update, dim3(cdiv(p, 64), cdiv(p, 64), nb), dim3(256), 0, s, p, k0, kb,
+        hipLaunchKernelGGL(k_panel, dim3(cdiv(p, 64), nb), dim3(256), 0, s, p, k0, kb, M, Q, W, Old);
+        hipLaunchKernelGGL(k_update, dim3(cdiv(p, 128), cdiv(p, 128), nb), dim3(256), 0, s, p, k0, kb,
                            M, W, Old, Q);
         UOI_LAUNCH_CHECK();
     }
