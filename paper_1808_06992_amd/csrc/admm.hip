@@ -63,22 +63,47 @@ struct AdmmEpi {
     }
     template <class Acc>
     __device__ void apply(int b, int i_base, int r0, int lr, int lk, Acc (&acc)[FM][FN]) const {
+        // all loads of the tile first (the stores below may not be reordered above
+        // them by the compiler), then the threshold / dual update and the stores
+        T hv[FM][4], uv[FN][FM][4];
+        bool act[FN];
 #pragma unroll
         for (int c = 0; c < FN; ++c) {
-            int r = r0 + 16 * c + lr;
-            if (r >= R || state[(size_t)b * R + r] != 0) continue;
-            int e = r % pe;
-            T thr = (T)lam[r / pe] * inv_rho;
+            const int r = r0 + 16 * c + lr;
+            act[c] = r < R && state[(size_t)b * R + r] == 0;
+        }
+#pragma unroll
+        for (int a = 0; a < FM; ++a)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int i = i_base + 16 * a + mfma_row(T(0), lk, t);
+#pragma unroll
+                for (int c = 0; c < FN; ++c) {
+                    const int r = r0 + 16 * c + lr;
+                    const bool ok = act[c] && i < p;
+                    uv[c][a][t] = ok ? u[((size_t)b * p + i) * R + r] : T(0);
+                    if (c == 0) hv[a][t] = T(0);
+                    if (ok && pe == 1) hv[a][t] = h[(size_t)b * p + i];
+                }
+            }
+#pragma unroll
+        for (int c = 0; c < FN; ++c) {
+            const int r = r0 + 16 * c + lr;
+            if (!act[c]) continue;
+            const int e = r % pe;
+            const T thr = (T)lam[r / pe] * inv_rho;
 #pragma unroll
             for (int a = 0; a < FM; ++a)
+#pragma unroll
                 for (int t = 0; t < 4; ++t) {
-                    int i = i_base + 16 * a + mfma_row(T(0), lk, t);
+                    const int i = i_base + 16 * a + mfma_row(T(0), lk, t);
                     if (i >= p) continue;
-                    size_t o = ((size_t)b * p + i) * R + r;
-                    T x = h[((size_t)b * p + i) * pe + e] + rho * (T)acc[a][c][t];
-                    T uo = u[o];
-                    T zn = soft_threshold(x + uo, thr);
-                    T un = uo + x - zn;
+                    const size_t o = ((size_t)b * p + i) * R + r;
+                    const T hh = pe == 1 ? hv[a][t] : h[((size_t)b * p + i) * pe + e];
+                    const T x = hh + rho * (T)acc[a][c][t];
+                    const T uo = uv[c][a][t];
+                    const T zn = soft_threshold(x + uo, thr);
+                    const T un = uo + x - zn;
                     z[o] = zn;
                     u[o] = un;
                     vout[o] = zn - un;

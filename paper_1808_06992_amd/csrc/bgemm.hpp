@@ -13,7 +13,11 @@
 //     step is 4 rows x 16 consecutive entries, loaded straight into registers;
 //     the loads of chunk c+1 are issued before the MFMAs of chunk c.
 // One barrier per chunk.  Every A element is read once per launch; V is read
-// once per row tile.
+// once per row tile.  (Measured alternatives: 64-row chunks, or a three-stage
+// register ring, both cost occupancy on float64 and ran slower.)
+// Workgroups are remapped so that all tiles of one matrix run on the same XCD:
+// the V block of a matrix is then re-read from that XCD's L2 instead of from
+// the fabric (the dispatcher deals workgroups to the 8 XCDs round robin).
 #pragma once
 #include <type_traits>
 
@@ -34,11 +38,12 @@ __global__ __launch_bounds__(256) void k_bgemm(int p, int R, const T *__restrict
     typedef typename AccT<T>::type acc_t;
     constexpr int TN = 16 * FN;
     __shared__ T Vs[2][BG_KC][TN];
-    const int b = blockIdx.z;
-    const int r0 = blockIdx.x * TN;
+    int bx, by, b;
+    xcd_tile(bx, by, b);
+    const int r0 = bx * TN;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wid = tid >> 6;
-    const int i_base = blockIdx.y * (64 * FM) + wid * (16 * FM);
+    const int i_base = by * (64 * FM) + wid * (16 * FM);
     const int lr = lane & 15, lk = lane >> 4;
     if (!epi.tile_active(b, r0, TN)) return;  // uniform over the workgroup
 

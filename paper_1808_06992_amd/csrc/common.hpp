@@ -81,6 +81,28 @@ __device__ __forceinline__ fx4 mfma16x16x4(float a, float b, fx4 c) {
 __device__ __forceinline__ int mfma_row(double, int lk, int t) { return lk + 4 * t; }
 __device__ __forceinline__ int mfma_row(float, int lk, int t) { return 4 * lk + t; }
 
+// XCD-aware workgroup order.  The dispatcher deals linear workgroup ids to the 8
+// XCDs round robin (id % 8), each XCD with its own L2.  xcd_remap turns the
+// linear id into a logical id such that every XCD receives one contiguous range
+// of logical ids (a bijection on [0, total) for any total).
+constexpr int kNumXcd = 8;
+__device__ __forceinline__ int xcd_remap(int L, int total) {
+    const int q = total / kNumXcd, r = total % kNumXcd;
+    const int x = L % kNumXcd, s = L / kNumXcd;
+    return x * q + min(x, r) + s;
+}
+// (x, y, z) of the logical workgroup, z slowest: tiles of one z stay on one XCD.
+__device__ __forceinline__ void xcd_tile(int &x, int &y, int &z) {
+    const int gx = gridDim.x, gy = gridDim.y;
+    const int total = gx * gy * gridDim.z;
+    const int L = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const int id = xcd_remap(L, total);
+    z = id / (gx * gy);
+    const int rem = id - z * gx * gy;
+    y = rem / gx;
+    x = rem - y * gx;
+}
+
 __device__ __forceinline__ double soft_threshold(double a, double t) {
     return a > t ? a - t : (a < -t ? a + t : 0.0);
 }

@@ -175,17 +175,24 @@ struct CgEpi {
         for (int c = 0; c < FN; ++c) {
             int r = r0 + 16 * c + lr;
             bool ok = r < nL && state[(size_t)b * nL + r] == 0;
-            double part = 0.0;
             const uint64_t *sw = ok ? supp + (size_t)Lidx[r] * W : nullptr;
+            double pv[FM][4];
+            bool mk[FM][4];
+            for (int a = 0; a < FM; ++a)  // loads before the stores of AP
+                for (int t = 0; t < 4; ++t) {
+                    int i = i_base + 16 * a + mfma_row(0.0, lk, t);
+                    bool in = ok && i < p;
+                    mk[a][t] = in && ((sw[i >> 6] >> (i & 63)) & 1ull);
+                    pv[a][t] = in ? P[((size_t)b * p + i) * nL + r] : 0.0;
+                }
+            double part = 0.0;
             for (int a = 0; a < FM; ++a)
                 for (int t = 0; t < 4; ++t) {
                     int i = i_base + 16 * a + mfma_row(0.0, lk, t);
                     if (!ok || i >= p) continue;
-                    bool m = (sw[i >> 6] >> (i & 63)) & 1ull;
-                    size_t o = ((size_t)b * p + i) * nL + r;
-                    double ap = m ? (double)acc[a][c][t] : 0.0;
-                    AP[o] = ap;
-                    part += P[o] * ap;
+                    double ap = mk[a][t] ? (double)acc[a][c][t] : 0.0;
+                    AP[((size_t)b * p + i) * nL + r] = ap;
+                    part += pv[a][t] * ap;
                 }
             part += __shfl_xor(part, 16);
             part += __shfl_xor(part, 32);
@@ -233,11 +240,24 @@ __global__ void k_cg_update(int p, int nL, const uint8_t *__restrict__ state,
     if (state[sc]) return;
     double den = pAp[sc];
     double alpha = den > 0.0 ? rr[sc] / den : 0.0;
+    double pv[4], xv[4], rv[4], av[4];
+    const int n = min(p, i0 + 4) - i0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        size_t o = ((size_t)k * p + i0 + t) * nL + c;
+        bool in = t < n;
+        pv[t] = in ? P[o] : 0.0;
+        xv[t] = in ? X[o] : 0.0;
+        rv[t] = in ? Rv[o] : 0.0;
+        av[t] = in ? AP[o] : 0.0;
+    }
     double part = 0.0;
-    for (int i = i0; i < min(p, i0 + 4); ++i) {
-        size_t o = ((size_t)k * p + i) * nL + c;
-        X[o] += alpha * P[o];
-        double r = Rv[o] - alpha * AP[o];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        if (t >= n) continue;
+        size_t o = ((size_t)k * p + i0 + t) * nL + c;
+        X[o] = xv[t] + alpha * pv[t];
+        double r = rv[t] - alpha * av[t];
         Rv[o] = r;
         part += r * r;
     }

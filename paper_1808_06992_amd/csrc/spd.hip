@@ -25,26 +25,46 @@ constexpr int SMALL = 88;  // whole-matrix in-LDS sweep up to this size (LDS <= 
 
 // Unblocked symmetric sweep of an n x n matrix held in LDS (row stride ld).
 // Leaves -A^{-1} in place.  256 threads; thread (ty, tx) = (tid/16, tid%16)
-// owns rows ty + 16a and columns tx + 16c.
+// owns rows ty + 16a and columns tx + 16c (n <= 96).
 __device__ void lds_sweep(double *A, int n, int ld) {
+    constexpr int MB = 6;  // rows / columns per thread: n <= 96
     const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
     for (int k = 0; k < n; ++k) {
         const double pinv = 1.0 / A[k * ld + k];
-        // update the off-pivot part first: it reads row/column k only
-        for (int i = ty; i < n; i += 16) {
-            if (i == k) continue;
-            const double aik = A[i * ld + k] * pinv;
-            for (int j = tx; j < n; j += 16)
-                if (j != k) A[i * ld + j] -= aik * A[k * ld + j];
+        // off-pivot update; it reads row and column k only, so every operand is
+        // loaded before any store of this phase
+        double ak[MB], rk[MB], v[MB][MB];
+#pragma unroll
+        for (int a = 0; a < MB; ++a) {
+            const int i = ty + 16 * a, j = tx + 16 * a;
+            ak[a] = i < n ? A[i * ld + k] * pinv : 0.0;
+            rk[a] = j < n ? A[k * ld + j] : 0.0;
         }
-        __syncthreads();
-        for (int i = threadIdx.x; i < n; i += blockDim.x)
-            if (i != k) {
-                A[i * ld + k] *= pinv;
-                A[k * ld + i] = A[i * ld + k];
+#pragma unroll
+        for (int a = 0; a < MB; ++a)
+#pragma unroll
+            for (int c = 0; c < MB; ++c) {
+                const int i = ty + 16 * a, j = tx + 16 * c;
+                v[a][c] = (i < n && j < n) ? A[i * ld + j] : 0.0;
+            }
+#pragma unroll
+        for (int a = 0; a < MB; ++a)
+#pragma unroll
+            for (int c = 0; c < MB; ++c) {
+                const int i = ty + 16 * a, j = tx + 16 * c;
+                if (i < n && j < n && i != k && j != k) A[i * ld + j] = v[a][c] - ak[a] * rk[c];
             }
         __syncthreads();
-        if (threadIdx.x == 0) A[k * ld + k] = -pinv;
+        // pivot row / column scaling and the pivot itself
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            if (i != k) {
+                const double x = A[i * ld + k] * pinv;
+                A[i * ld + k] = x;
+                A[k * ld + i] = x;
+            } else {
+                A[k * ld + k] = -pinv;
+            }
+        }
         __syncthreads();
     }
 }
@@ -160,8 +180,9 @@ __global__ __launch_bounds__(256, 2) void k_update(int p, int k0, int kb, double
     constexpr int QK = 16, LD = 128 + 1;
     __shared__ double Ws[QK * LD];
     __shared__ double Os[QK * LD];
-    const int b = blockIdx.z;
-    const int i0 = blockIdx.y * 128, j0 = blockIdx.x * 128;
+    int bx, by, b;
+    xcd_tile(bx, by, b);  // all tiles of one matrix on one XCD: W, Old stay in its L2
+    const int i0 = by * 128, j0 = bx * 128;
     const double *Wb = W + (size_t)b * p * NB;
     const double *Ob = Old + (size_t)b * p * NB;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -196,8 +217,19 @@ __global__ __launch_bounds__(256, 2) void k_update(int p, int k0, int kb, double
     }
     double *Ab = A + (size_t)b * p * p;
     const double *Qb = Q + (size_t)b * NB * NB;
+    const bool plain = !(i0 < k0 + kb && i0 + 128 > k0) && !(j0 < k0 + kb && j0 + 128 > k0);
 #pragma unroll
-    for (int fm = 0; fm < 4; ++fm)
+    for (int fm = 0; fm < 4; ++fm) {
+        // read-modify-write one 16-row band: loads first, then stores
+        double old[4][4];
+#pragma unroll
+        for (int fn = 0; fn < 4; ++fn)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int i = i0 + wm * 64 + fm * 16 + mfma_row(0.0, lk, t);
+                const int j = j0 + wn * 64 + fn * 16 + lr;
+                old[fn][t] = (i < p && j < p) ? Ab[(size_t)i * p + j] : 0.0;
+            }
 #pragma unroll
         for (int fn = 0; fn < 4; ++fn)
 #pragma unroll
@@ -205,13 +237,16 @@ __global__ __launch_bounds__(256, 2) void k_update(int p, int k0, int kb, double
                 const int i = i0 + wm * 64 + fm * 16 + mfma_row(0.0, lk, t);
                 const int j = j0 + wn * 64 + fn * 16 + lr;
                 if (i >= p || j >= p) continue;
-                const bool iK = i >= k0 && i < k0 + kb, jK = j >= k0 && j < k0 + kb;
-                double *dst = Ab + (size_t)i * p + j;
-                if (!iK && !jK) *dst -= acc[fm][fn][t];                 // A_ij - A_iK Q A_Kj
-                else if (!iK) *dst = Wb[(size_t)i * NB + (j - k0)];      // A_iK Q
-                else if (!jK) *dst = Wb[(size_t)j * NB + (i - k0)];      // Q A_Kj = (A_jK Q)'
-                else *dst = -Qb[(i - k0) * NB + (j - k0)];               // -Q
+                double v = old[fn][t] - acc[fm][fn][t];             // A_ij - A_iK Q A_Kj
+                if (!plain) {
+                    const bool iK = i >= k0 && i < k0 + kb, jK = j >= k0 && j < k0 + kb;
+                    if (iK && jK) v = -Qb[(i - k0) * NB + (j - k0)];      // -Q
+                    else if (jK) v = Wb[(size_t)i * NB + (j - k0)];       // A_iK Q
+                    else if (iK) v = Wb[(size_t)j * NB + (i - k0)];       // Q A_Kj = (A_jK Q)'
+                }
+                Ab[(size_t)i * p + j] = v;
             }
+    }
 }
 
 size_t spd_inverse_work_doubles(int nb, int p) {
