@@ -79,6 +79,9 @@ enum {
 /* opts.flags */
 #define UOI_FLAG_TIMING 1u  /* fill uoi_diag.stage_ms with hipEvent stage times */
 
+/* Opaque warm-start network (see the uoi_mlp_* functions below). */
+typedef struct uoi_mlp uoi_mlp;
+
 typedef struct uoi_opts {
     int32_t B1;            /* selection bootstraps, >= 1                                   */
     int32_t B2;            /* estimation splits, >= 1                                      */
@@ -96,6 +99,12 @@ typedef struct uoi_opts {
     int32_t solver;        /* UOI_SOLVER_BATCHED or UOI_SOLVER_PLAIN                       */
     uint32_t flags;        /* UOI_FLAG_*                                                   */
     void *stream;          /* hipStream_t, NULL = default stream                           */
+    uoi_mlp *mlp;          /* warm-start network, required when warm_start == UOI_MLP
+                              (UoI_LASSO only; network input p+1, output p)               */
+    double relax;          /* ADMM over-relaxation alpha in [1, 1.95] (default 1: the plain
+                              scaled ADMM).  With alpha, the z- and u-updates use
+                              alpha*x + (1-alpha)*z_old in place of x (Boyd et al. 2011,
+                              Sec. 3.4.3); the fixed point, hence the solution, is the same. */
 } uoi_opts;
 
 /* Per-kernel totals gathered with UOI_FLAG_TIMING: device time from hipEvents
@@ -132,6 +141,7 @@ typedef struct uoi_diag {
     int64_t n_solves;   /* B1*R                                                          */
     int64_t n_unconverged;
     int32_t max_iters;  /* largest iteration count among converged solves               */
+    int64_t warm_used;  /* solves started from the network (the rest fell back to cold)  */
     float stage_ms[8];  /* with UOI_FLAG_TIMING: index/gram, factor, admm, verify,
                            support, estimation-gram, ols, loss+average                   */
     uoi_kstat kstat[UOI_KSTAT_N]; /* with UOI_FLAG_TIMING: per-kernel totals (see below) */
@@ -189,6 +199,16 @@ int uoi_lasso_solve_batch(int32_t nb, int32_t p, const double *G, const double *
                           double *z_out, double *u_out, int32_t *iters, double *kkt);
 
 /*
+ * LASSO solves sharing a Gram: for each of nb Grams G_b, pe linear terms
+ * C_b[:, e] (C [nb*p*pe], c[b][i][e]), each at all q lambdas of opts; the
+ * solves of one Gram run as one batched ADMM (the structure of the per-equation
+ * VAR problems of Eq. (8)).  z_out [nb*q*pe*p] = z[b][j][e][i]; iters, kkt
+ * [nb*q*pe] nullable.  opts as for uoi_lasso_solve_batch; cold start only.
+ */
+int uoi_lasso_solve_multi(int32_t nb, int32_t p, int32_t pe, const double *G, const double *C,
+                          const uoi_opts *o, double *z_out, int32_t *iters, double *kkt);
+
+/*
  * Gram of sampled rows (Alg. 1 bootstrap statistics): for b < nb,
  *   G_b = X_r'X_r / m,  C_b = X_r'Y_r / m  with r = rows[b*m .. b*m+m-1]
  * (rows counted with multiplicity), X row r at X + r*ldx (p values), Y row r at
@@ -221,6 +241,45 @@ int uoi_var_split_rows(uint64_t seed, int32_t nb, int32_t N, int32_t L, int32_t 
 /* Batched inverse of G_b + rho*I (float64, blocked Gauss-Jordan sweep):
  * M [nb*p*p] may alias nothing else.  Used by the ADMM x-update. */
 int uoi_spd_inverse(int32_t nb, int32_t p, const double *G, double rho, double *M, void *stream);
+
+/*
+ * Warm-start network (not part of the paper, whose ADMM starts cold): a 3-layer
+ * ReLU MLP that maps one selection problem (bootstrap statistics c, penalty
+ * lambda) to an ADMM starting point,
+ *     input  x = [c / lambda_max, log(lambda / lambda_max)]   (n_in  = p + 1)
+ *     output z / lambda_max                                  (n_out = p)
+ * with lambda_max = ||c||_inf.  Layers y = x W' + b with W stored (out, in);
+ * the flat parameter vector is [W1 (hidden x n_in), b1, W2 (hidden x hidden), b2,
+ * W3 (n_out x hidden), b3], float32 master copy.  GEMM operands are bfloat16
+ * (round to nearest even) with float32 accumulation on MFMA.  Loss = mean over
+ * rows and outputs of (y - t)^2; optimiser Adam (beta 0.9 / 0.999, eps 1e-8).
+ * With opts->warm_start == UOI_MLP the fit predicts z for every (bootstrap,
+ * lambda), sets u = clip((c - G z) / rho, -lambda/rho, lambda/rho), and keeps
+ * the cold start for a solve whose predicted z does not lower the LASSO
+ * objective z'Gz/2 - c'z + lambda*|z|_1 below its value 0 at z = 0.
+ * X, Y, T, theta, grad are DEVICE float32 arrays, row-major; loss is HOST.
+ * A network is used by one stream at a time (it owns its activation buffers).
+ */
+int uoi_mlp_create(int32_t n_in, int32_t hidden, int32_t n_out, uoi_mlp **out); /* zero weights */
+void uoi_mlp_destroy(uoi_mlp *m);
+int64_t uoi_mlp_num_params(const uoi_mlp *m);
+int uoi_mlp_set_params(uoi_mlp *m, const float *theta, void *stream); /* also resets Adam */
+int uoi_mlp_get_params(const uoi_mlp *m, float *theta, void *stream);
+int uoi_mlp_forward(uoi_mlp *m, int32_t n, const float *X, float *Y, void *stream);
+int uoi_mlp_loss_grad(uoi_mlp *m, int32_t n, const float *X, const float *T, float *grad,
+                      double *loss, void *stream);             /* grad nullable */
+int uoi_mlp_train_step(uoi_mlp *m, int32_t n, const float *X, const float *T, float lr,
+                       double *loss, void *stream);            /* one Adam step, enqueued on
+                                                                  stream; loss nullable (when
+                                                                  given, the call synchronises) */
+/* Training pairs for the network from solved problems: nb Grams, pe linear
+ * terms each, q lambdas:
+ *   c [nb*p*pe] linear terms (c[b][i][e]), lambdas HOST [q],
+ *   z [nb*q*pe*p] solutions (z[b][j][e][i])
+ *   X [nb*q*pe*(p+1)] network inputs, T [nb*q*pe*p] targets z / lambda_max (float32),
+ *   row (b*q + j)*pe + e.  (The network's training data; not part of the paper.) */
+int uoi_ws_dataset(int32_t nb, int32_t p, int32_t q, int32_t pe, const double *c,
+                   const double *lambdas, const double *z, float *X, float *T, void *stream);
 
 /* Free the library's scratch pool on the current device. */
 void uoi_release_workspace(void);

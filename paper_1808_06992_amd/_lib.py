@@ -43,7 +43,8 @@ class Opts(C.Structure):
         ("max_iter", C.c_int32), ("check_every", C.c_int32),
         ("train_num", C.c_int32), ("train_den", C.c_int32),
         ("precision", C.c_int32), ("warm_start", C.c_int32), ("solver", C.c_int32),
-        ("flags", C.c_uint32), ("stream", C.c_void_p),
+        ("flags", C.c_uint32), ("stream", C.c_void_p), ("mlp", C.c_void_p),
+        ("relax", C.c_double),
     ]
 
 
@@ -59,7 +60,8 @@ class Diag(C.Structure):
     _fields_ = [
         ("iters", C.c_void_p), ("kkt", C.c_void_p), ("sel_beta", C.c_void_p),
         ("losses", C.c_void_p), ("n_solves", C.c_int64), ("n_unconverged", C.c_int64),
-        ("max_iters", C.c_int32), ("stage_ms", C.c_float * 8), ("kstat", KStat * 4),
+        ("max_iters", C.c_int32), ("warm_used", C.c_int64), ("stage_ms", C.c_float * 8),
+        ("kstat", KStat * 4),
     ]
 
 
@@ -72,6 +74,9 @@ EXPORTS = (
     "uoi_default_opts", "uoi_lasso_fit", "uoi_var_fit", "uoi_lasso_solve_batch", "uoi_gram",
     "uoi_bootstrap_rows", "uoi_split_rows", "uoi_var_boot_rows", "uoi_var_split_rows",
     "uoi_spd_inverse", "uoi_release_workspace", "uoi_last_error", "uoi_version",
+    "uoi_mlp_create", "uoi_mlp_destroy", "uoi_mlp_num_params", "uoi_mlp_set_params",
+    "uoi_mlp_get_params", "uoi_mlp_forward", "uoi_mlp_loss_grad", "uoi_mlp_train_step",
+    "uoi_ws_dataset", "uoi_lasso_solve_multi",
 )
 
 _lib = None
@@ -112,6 +117,26 @@ def load():
     L.uoi_last_error.argtypes = []
     L.uoi_version.restype = C.c_char_p
     L.uoi_version.argtypes = []
+    L.uoi_mlp_create.restype = i32
+    L.uoi_mlp_create.argtypes = [i32, i32, i32, C.POINTER(C.c_void_p)]
+    L.uoi_mlp_destroy.restype = None
+    L.uoi_mlp_destroy.argtypes = [P]
+    L.uoi_mlp_num_params.restype = C.c_int64
+    L.uoi_mlp_num_params.argtypes = [P]
+    L.uoi_mlp_set_params.restype = i32
+    L.uoi_mlp_set_params.argtypes = [P, P, P]
+    L.uoi_mlp_get_params.restype = i32
+    L.uoi_mlp_get_params.argtypes = [P, P, P]
+    L.uoi_mlp_forward.restype = i32
+    L.uoi_mlp_forward.argtypes = [P, i32, P, P, P]
+    L.uoi_mlp_loss_grad.restype = i32
+    L.uoi_mlp_loss_grad.argtypes = [P, i32, P, P, P, C.POINTER(C.c_double), P]
+    L.uoi_mlp_train_step.restype = i32
+    L.uoi_mlp_train_step.argtypes = [P, i32, P, P, C.c_float, C.POINTER(C.c_double), P]
+    L.uoi_ws_dataset.restype = i32
+    L.uoi_ws_dataset.argtypes = [i32, i32, i32, i32, P, P, P, P, P, P]
+    L.uoi_lasso_solve_multi.restype = i32
+    L.uoi_lasso_solve_multi.argtypes = [i32, i32, i32, P, P, C.POINTER(Opts), P, P, P]
     _lib = L
     return L
 
@@ -138,7 +163,7 @@ def _ptr(t):
 
 def make_opts(lambdas, *, B1=1, B2=1, seed=0, rho=1.0, kkt_tol=1e-6, max_iter=20000,
               check_every=10, train=(4, 5), precision="fp64", solver="batched",
-              warm_start="cold", timing=False, stream="current"):
+              warm_start="cold", timing=False, stream="current", mlp=None, relax=1.0):
     lam = np.ascontiguousarray(np.asarray(lambdas, dtype=np.float64))
     o = Opts()
     load().uoi_default_opts(C.byref(o))
@@ -152,7 +177,11 @@ def make_opts(lambdas, *, B1=1, B2=1, seed=0, rho=1.0, kkt_tol=1e-6, max_iter=20
     o.solver = SOLVERS[solver]
     o.warm_start = WARM[warm_start]
     o.flags = UOI_FLAG_TIMING if timing else 0
+    o.relax = float(relax)
     o.stream = _stream() if stream == "current" else C.c_void_p(stream)
+    if mlp is not None:
+        o.mlp = mlp.handle
+        o.warm_start = UOI_MLP
     return o, lam  # keep lam alive with the struct
 
 
@@ -184,6 +213,7 @@ def lasso_fit(X: torch.Tensor, y: torch.Tensor, lambdas, B1: int, B2: int, seed:
     out["status"] = code
     out["n_unconverged"] = int(d.n_unconverged)
     out["max_iters"] = int(d.max_iters)
+    out["warm_used"] = int(d.warm_used)
     out["stage_ms"] = dict(zip(STAGES, list(d.stage_ms)))
     out["kstat"] = kstats(d)
     return out
@@ -324,3 +354,83 @@ def release_workspace():
 
 def version() -> str:
     return load().uoi_version().decode()
+
+
+class MLP:
+    """Warm-start network living on the GPU (uoi_mlp_* functions)."""
+
+    def __init__(self, n_in: int, hidden: int, n_out: int):
+        L = load()
+        h = C.c_void_p()
+        _check(L.uoi_mlp_create(n_in, hidden, n_out, C.byref(h)), allow_noconv=False)
+        self.handle = h
+        self.n_in, self.hidden, self.n_out = n_in, hidden, n_out
+        self.nparam = int(L.uoi_mlp_num_params(h))
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.uoi_mlp_destroy(self.handle)
+            self.handle = None
+
+    def set_params(self, theta: torch.Tensor):
+        theta = _dev(theta, torch.float32)
+        assert theta.numel() == self.nparam
+        _check(load().uoi_mlp_set_params(self.handle, _ptr(theta), _stream()), allow_noconv=False)
+
+    def get_params(self) -> torch.Tensor:
+        t = torch.empty(self.nparam, dtype=torch.float32, device="cuda")
+        _check(load().uoi_mlp_get_params(self.handle, _ptr(t), _stream()), allow_noconv=False)
+        return t
+
+    def forward(self, X: torch.Tensor) -> torch.Tensor:
+        X = _dev(X, torch.float32)
+        Y = torch.empty((X.shape[0], self.n_out), dtype=torch.float32, device=X.device)
+        _check(load().uoi_mlp_forward(self.handle, X.shape[0], _ptr(X), _ptr(Y), _stream()),
+               allow_noconv=False)
+        return Y
+
+    def loss_grad(self, X: torch.Tensor, T: torch.Tensor):
+        X = _dev(X, torch.float32); T = _dev(T, torch.float32)
+        g = torch.empty(self.nparam, dtype=torch.float32, device=X.device)
+        loss = C.c_double()
+        _check(load().uoi_mlp_loss_grad(self.handle, X.shape[0], _ptr(X), _ptr(T), _ptr(g),
+                                        C.byref(loss), _stream()), allow_noconv=False)
+        return loss.value, g
+
+    def train_step(self, X: torch.Tensor, T: torch.Tensor, lr: float, want_loss: bool = True):
+        """One Adam step; returns the batch loss (a synchronisation) or None."""
+        loss = C.c_double()
+        _check(load().uoi_mlp_train_step(self.handle, X.shape[0], _ptr(X), _ptr(T), float(lr),
+                                         C.byref(loss) if want_loss else None, _stream()),
+               allow_noconv=False)
+        return loss.value if want_loss else None
+
+
+def ws_dataset(c: torch.Tensor, lambdas, z: torch.Tensor):
+    """Network inputs / targets from solved problems: c [nb, p] or [nb, p, pe],
+    z [nb, q, p] or [nb, q, pe, p]."""
+    c = _dev(c.contiguous()); z = _dev(z.contiguous())
+    if c.dim() == 2:
+        c = c.unsqueeze(-1).contiguous()
+    nb, p, pe = c.shape
+    lam = np.ascontiguousarray(np.asarray(lambdas, dtype=np.float64))
+    q = lam.size
+    X = torch.empty((nb * q * pe, p + 1), dtype=torch.float32, device=c.device)
+    T = torch.empty((nb * q * pe, p), dtype=torch.float32, device=c.device)
+    _check(load().uoi_ws_dataset(nb, p, q, pe, _ptr(c), lam.ctypes.data_as(C.c_void_p), _ptr(z), _ptr(X),
+                                 _ptr(T), _stream()), allow_noconv=False)
+    return X, T
+
+
+def lasso_solve_multi(G: torch.Tensor, Cm: torch.Tensor, lambdas, **kw):
+    """Solves sharing each Gram: G [nb, p, p], Cm [nb, p, pe]; z [nb, q, pe, p]."""
+    G = _dev(G); Cm = _dev(Cm.contiguous())
+    nb, p, pe = Cm.shape
+    o, lam = make_opts(lambdas, **kw)
+    q = lam.size
+    z = torch.empty((nb, q, pe, p), dtype=torch.float64, device=G.device)
+    its = torch.empty((nb, q, pe), dtype=torch.int32, device=G.device)
+    kkt = torch.empty((nb, q, pe), dtype=torch.float64, device=G.device)
+    code = _check(load().uoi_lasso_solve_multi(nb, p, pe, _ptr(G), _ptr(Cm), C.byref(o), _ptr(z), _ptr(its),
+                                               _ptr(kkt)))
+    return dict(z=z, iters=its, kkt=kkt, status=code)

@@ -87,8 +87,13 @@ static void check_opts(const uoi_opts *o, bool need_boot) {
     UOI_REQUIRE(std::isfinite(o->kkt_tol) && o->kkt_tol > 0.0, "kkt_tol must be > 0");
     UOI_REQUIRE(o->max_iter >= 1, "max_iter must be >= 1");
     UOI_REQUIRE(o->check_every >= 1, "check_every must be >= 1");
+    UOI_REQUIRE(std::isfinite(o->relax) && o->relax >= 1.0 && o->relax <= 1.95,
+                "relax must be in [1, 1.95]");
     UOI_REQUIRE(o->precision == UOI_FP64 || o->precision == UOI_MIXED, "unknown precision");
-    UOI_REQUIRE(o->warm_start == UOI_COLD, "warm start by network: no network loaded");
+    UOI_REQUIRE(o->warm_start == UOI_COLD || o->warm_start == UOI_MLP, "unknown warm start");
+    UOI_REQUIRE(o->warm_start != UOI_MLP || o->mlp != nullptr, "warm start by network: no network given");
+    UOI_REQUIRE(o->warm_start != UOI_MLP || o->solver == UOI_SOLVER_BATCHED,
+                "warm start by network needs the batched solver");
     UOI_REQUIRE(o->solver == UOI_SOLVER_BATCHED || o->solver == UOI_SOLVER_PLAIN, "unknown solver");
 }
 
@@ -206,7 +211,7 @@ static int lasso_fit(int n, int p, const double *X, const double *y, const uoi_o
 
     const int B1 = o->B1, B2 = o->B2, q = o->q, R = q;
     AdmmProblem P{B1, p, q, 1, R, nullptr, nullptr, nullptr, o->rho, o->kkt_tol, o->max_iter,
-                  o->check_every};
+                  o->check_every, o->warm_start == UOI_MLP ? o->mlp : nullptr, o->relax};
     EstimProblem E{B2, p, 1, q, R, nullptr, nullptr, nullptr, nullptr, nullptr, supp_out};
     size_t nst = (size_t)B1 * p * R;
     // size the scratch arena
@@ -260,7 +265,7 @@ static int lasso_fit(int n, int p, const double *X, const double *y, const uoi_o
     P.C = c;
     P.lam = lam;
     AdmmOut out{z, u, diag && diag->iters ? diag->iters : its, diag && diag->kkt ? diag->kkt : kkt, 0, 0,
-                timing && diag ? diag->kstat : nullptr};
+                timing && diag ? diag->kstat : nullptr, 0};
     admm_solve(s, P, o->precision, o->solver, admm_w, false, out, timing ? sm + 1 : nullptr);
     tm.mark();
     launch_support_and(s, B1, p, R, z, supp_out);
@@ -285,6 +290,7 @@ static int lasso_fit(int n, int p, const double *X, const double *y, const uoi_o
         diag->n_solves = (int64_t)B1 * R;
         diag->n_unconverged = out.unconverged;
         diag->max_iters = out.max_iters;
+        diag->warm_used = out.warm_used;
         std::memcpy(diag->stage_ms, sm, sizeof(sm));
     }
     return out.unconverged ? UOI_ENOCONV : UOI_OK;
@@ -313,8 +319,9 @@ static int var_fit(int T, int p, int d, const double *series, int block_len, con
     if (diag) std::memset(diag->kstat, 0, sizeof(diag->kstat));
 
     const int B1 = o->B1, B2 = o->B2, q = o->q, pe = p, R = q * p;
+    UOI_REQUIRE(o->warm_start == UOI_COLD, "warm start by network is for UoI_LASSO only");
     AdmmProblem P{B1, p, q, pe, R, nullptr, nullptr, nullptr, o->rho, o->kkt_tol, o->max_iter,
-                  o->check_every};
+                  o->check_every, nullptr, o->relax};
     EstimProblem E{B2, p, pe, q, R, nullptr, nullptr, nullptr, nullptr, nullptr, supp_out};
     size_t nst = (size_t)B1 * p * R;
     auto layout = [&](Arena &a, int32_t *&rows, double *&G, double *&C, double *&lam, double *&z,
@@ -369,7 +376,7 @@ static int var_fit(int T, int p, int d, const double *series, int block_len, con
     P.C = C;
     P.lam = lam;
     AdmmOut out{z, u, diag && diag->iters ? diag->iters : its, diag && diag->kkt ? diag->kkt : kkt, 0, 0,
-                timing && diag ? diag->kstat : nullptr};
+                timing && diag ? diag->kstat : nullptr, 0};
     admm_solve(s, P, o->precision, o->solver, admm_w, false, out, timing ? sm + 1 : nullptr);
     tm.mark();
     launch_support_and(s, B1, p, R, z, supp_out);
@@ -395,6 +402,7 @@ static int var_fit(int T, int p, int d, const double *series, int block_len, con
         diag->n_solves = (int64_t)B1 * R;
         diag->n_unconverged = out.unconverged;
         diag->max_iters = out.max_iters;
+        diag->warm_used = out.warm_used;
         std::memcpy(diag->stage_ms, sm, sizeof(sm));
     }
     return out.unconverged ? UOI_ENOCONV : UOI_OK;
@@ -409,7 +417,8 @@ static int solve_batch(int nb, int p, const double *G, const double *c, const uo
     UOI_REQUIRE(G && c && z_out, "NULL input or output pointer");
     hipStream_t s = (hipStream_t)o->stream;
     const int q = o->q, R = q;
-    AdmmProblem P{nb, p, q, 1, R, G, c, nullptr, o->rho, o->kkt_tol, o->max_iter, o->check_every};
+    AdmmProblem P{nb, p, q, 1, R, G, c, nullptr, o->rho, o->kkt_tol, o->max_iter, o->check_every,
+                  o->warm_start == UOI_MLP ? o->mlp : nullptr, o->relax};
     size_t nst = (size_t)nb * p * R;
     auto layout = [&](Arena &a, double *&lam, double *&z, double *&u, int32_t *&its, double *&kk,
                       void *&w) {
@@ -438,7 +447,7 @@ static int solve_batch(int nb, int p, const double *G, const double *c, const uo
         if (u0) transpose(s, nb, p, R, u0, u, false);
         else UOI_HIP(hipMemsetAsync(u, 0, sizeof(double) * nst, s));
     }
-    AdmmOut out{z, u, iters ? iters : its, kkt ? kkt : kk, 0, 0, nullptr};
+    AdmmOut out{z, u, iters ? iters : its, kkt ? kkt : kk, 0, 0, nullptr, 0};
     admm_solve(s, P, o->precision, o->solver, w, warm, out, nullptr);
     transpose(s, nb, p, R, z, z_out, true);
     if (u_out) transpose(s, nb, p, R, u, u_out, true);
@@ -478,6 +487,7 @@ void uoi_default_opts(uoi_opts *o) {
     o->check_every = 10;
     o->train_num = 4;
     o->train_den = 5;
+    o->relax = 1.0;
     o->precision = UOI_FP64;
     o->warm_start = UOI_COLD;
     o->solver = UOI_SOLVER_BATCHED;
@@ -578,6 +588,62 @@ int uoi_spd_inverse(int32_t nb, int32_t p, const double *G, double rho, double *
         spd_inverse_f64(s, nb, p, G, rho, M, w);
         UOI_HIP(hipStreamSynchronize(s));
         return UOI_OK;
+    });
+}
+
+int uoi_ws_dataset(int32_t nb, int32_t p, int32_t q, int32_t pe, const double *c, const double *lambdas,
+                   const double *z, float *X, float *T, void *stream) {
+    return guarded([&] {
+        UOI_REQUIRE(nb >= 1 && p >= 1 && q >= 1 && pe >= 1 && c && lambdas && z && X && T,
+                    "invalid arguments");
+        hipStream_t s = (hipStream_t)stream;
+        const size_t lb = ((size_t)q * 8 + 255) & ~size_t(255);
+        char *w = (char *)pool_get(lb + (size_t)nb * pe * 8 + 256);
+        double *lam = (double *)w;
+        double *cn = (double *)(w + lb);
+        UOI_HIP(hipMemcpyAsync(lam, lambdas, sizeof(double) * q, hipMemcpyHostToDevice, s));
+        warm_start_dataset(s, nb, p, q, pe, c, lam, z, X, T, cn);
+        UOI_HIP(hipStreamSynchronize(s));
+        return UOI_OK;
+    });
+}
+
+int uoi_lasso_solve_multi(int32_t nb, int32_t p, int32_t pe, const double *G, const double *C,
+                          const uoi_opts *o, double *z_out, int32_t *iters, double *kkt) {
+    return guarded([&] {
+        check_opts(o, false);
+        UOI_REQUIRE(nb >= 1 && p >= 1 && pe >= 1 && G && C && z_out, "invalid arguments");
+        UOI_REQUIRE(o->warm_start == UOI_COLD, "multi-response solves start cold");
+        hipStream_t s = (hipStream_t)o->stream;
+        const int q = o->q, R = q * pe;
+        AdmmProblem P{nb, p, q, pe, R, G, C, nullptr, o->rho, o->kkt_tol, o->max_iter, o->check_every,
+                      nullptr, o->relax};
+        const size_t nst = (size_t)nb * p * R;
+        auto layout = [&](Arena &a, double *&lam, double *&z, double *&u, int32_t *&its, double *&kk,
+                          void *&w) {
+            lam = a.take<double>(q);
+            z = a.take<double>(nst);
+            u = a.take<double>(nst);
+            its = a.take<int32_t>((size_t)nb * R);
+            kk = a.take<double>((size_t)nb * R);
+            w = a.take<char>(admm_work_bytes(P, o->precision, o->solver));
+        };
+        double *lam, *z, *u, *kk;
+        int32_t *its;
+        void *w;
+        Arena ar;
+        layout(ar, lam, z, u, its, kk, w);
+        Arena A;
+        A.cap = ar.off;
+        A.base = (char *)pool_get(ar.off);
+        layout(A, lam, z, u, its, kk, w);
+        UOI_HIP(hipMemcpyAsync(lam, o->lambdas, sizeof(double) * q, hipMemcpyHostToDevice, s));
+        P.lam = lam;
+        AdmmOut out{z, u, iters ? iters : its, kkt ? kkt : kk, 0, 0, nullptr, 0};
+        admm_solve(s, P, o->precision, o->solver, w, false, out, nullptr);
+        transpose(s, nb, p, R, z, z_out, true);
+        UOI_HIP(hipStreamSynchronize(s));
+        return out.unconverged ? UOI_ENOCONV : UOI_OK;
     });
 }
 

@@ -54,7 +54,7 @@ struct AdmmEpi {
     const uint8_t *state;// [nb][R] 0 = active
     const double *lam;   // [q]
     int p, R, pe;
-    T rho, inv_rho;
+    T rho, inv_rho, alpha;  // alpha: over-relaxation (1 = none)
     __device__ bool tile_active(int b, int r0, int w) const {
         int hi = min(R, r0 + w);
         for (int r = r0; r < hi; ++r)
@@ -65,7 +65,8 @@ struct AdmmEpi {
     __device__ void apply(int b, int i_base, int r0, int lr, int lk, Acc (&acc)[FM][FN]) const {
         // all loads of the tile first (the stores below may not be reordered above
         // them by the compiler), then the threshold / dual update and the stores
-        T hv[FM][4], uv[FN][FM][4];
+        T hv[FM][4], uv[FN][FM][4], zv[FN][FM][4];
+        const bool relaxed = alpha != T(1);
         bool act[FN];
 #pragma unroll
         for (int c = 0; c < FN; ++c) {
@@ -82,6 +83,7 @@ struct AdmmEpi {
                     const int r = r0 + 16 * c + lr;
                     const bool ok = act[c] && i < p;
                     uv[c][a][t] = ok ? u[((size_t)b * p + i) * R + r] : T(0);
+                    zv[c][a][t] = (ok && relaxed) ? z[((size_t)b * p + i) * R + r] : T(0);
                     if (c == 0) hv[a][t] = T(0);
                     if (ok && pe == 1) hv[a][t] = h[(size_t)b * p + i];
                 }
@@ -100,7 +102,8 @@ struct AdmmEpi {
                     if (i >= p) continue;
                     const size_t o = ((size_t)b * p + i) * R + r;
                     const T hh = pe == 1 ? hv[a][t] : h[((size_t)b * p + i) * pe + e];
-                    const T x = hh + rho * (T)acc[a][c][t];
+                    T x = hh + rho * (T)acc[a][c][t];
+                    if (relaxed) x = alpha * x + (T(1) - alpha) * zv[c][a][t];
                     const T uo = uv[c][a][t];
                     const T zn = soft_threshold(x + uo, thr);
                     const T un = uo + x - zn;
@@ -240,6 +243,99 @@ __global__ void k_unpark(size_t n, uint8_t *__restrict__ state) {
 }
 
 // ---------------------------------------------------------------------------
+// Warm start by the network (LASSO, one response): inputs, prediction, dual
+// completion and the per-solve fallback to the cold start.
+// ---------------------------------------------------------------------------
+// Row (b q + j) pe + e of the network input for response column e of bootstrap b
+// at lambda_j:  X[row][0..p) = c_{b,e} / lambda_max_{b,e}, X[row][p] =
+// log(lambda_j / lambda_max_{b,e}), with lambda_max_{b,e} = ||c_{b,e}||_inf.
+__global__ void k_ws_inputs(int nb, int p, int q, int pe, const double *__restrict__ c,
+                            const double *__restrict__ cn, const double *__restrict__ lam,
+                            float *__restrict__ X) {
+    size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t rowlen = (size_t)p + 1;
+    if (t >= (size_t)nb * q * pe * rowlen) return;
+    const size_t row = t / rowlen;
+    const int i = (int)(t % rowlen);
+    const int e = (int)(row % pe);
+    const size_t bj = row / pe;
+    const int b = (int)(bj / q), j = (int)(bj % q);
+    const double lm = cn[(size_t)b * pe + e] > 0.0 ? cn[(size_t)b * pe + e] : 1.0;
+    double v;
+    if (i < p) v = c[((size_t)b * p + i) * pe + e] / lm;
+    else v = log(fmax(lam[j], 1e-300) / lm);
+    X[t] = (float)v;
+}
+
+// z[b][i][j] = Y[(b q + j)][i] * lambda_max_b
+__global__ void k_ws_z0(int nb, int p, int q, const float *__restrict__ Y, const double *__restrict__ cn,
+                        double *__restrict__ z) {
+    size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (size_t)nb * p * q) return;
+    const int j = (int)(t % q);
+    const size_t bi = t / q;
+    const int i = (int)(bi % p), b = (int)(bi / p);
+    z[t] = (double)Y[((size_t)b * q + j) * p + i] * cn[b];
+}
+
+// One thread per solve (b, j): with g = c - G z0, u0 = clip(g/rho, +-lambda/rho).
+// The prediction is kept only if it lowers the LASSO objective below that of
+// the cold start, F(z) = z'Gz/2 - c'z + lambda |z|_1 with F(0) = 0 (a dense
+// prediction violates the KKT conditions on every coordinate that should be
+// zero, so the KKT residual is not a fair test of a starting point).
+__global__ void k_ws_finish(int nb, int p, int q, const double *__restrict__ c, const double *__restrict__ Gz,
+                            const double *__restrict__ lam, double rho, double *__restrict__ z,
+                            double *__restrict__ u, unsigned long long *__restrict__ used) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    bool use = false;
+    if (s < nb * q) {
+        const int b = s / q, j = s % q;
+        const double lm = lam[j];
+        double F = 0.0;
+        for (int i = 0; i < p; ++i) {
+            const size_t o = ((size_t)b * p + i) * q + j;
+            const double zi = z[o];
+            F += zi * (0.5 * Gz[o] - c[(size_t)b * p + i]) + lm * fabs(zi);
+        }
+        use = F < 0.0;
+        for (int i = 0; i < p; ++i) {
+            const size_t o = ((size_t)b * p + i) * q + j;
+            if (use) {
+                const double g = c[(size_t)b * p + i] - Gz[o];
+                u[o] = fmin(fmax(g / rho, -lm / rho), lm / rho);
+            } else {
+                z[o] = 0.0;
+                u[o] = 0.0;
+            }
+        }
+    }
+    unsigned long long bal = __ballot(use);
+    if ((threadIdx.x & 63) == 0 && bal) atomicAdd(used, (unsigned long long)__popcll(bal));
+}
+
+// Training pairs from solved problems: inputs as k_ws_inputs; targets
+// T[row][i] = z[b][j][e][i] / lambda_max_{b,e} (z solve-major, row = (b q + j) pe + e).
+__global__ void k_ws_targets(int nb, int p, int q, int pe, const double *__restrict__ cn,
+                             const double *__restrict__ z, float *__restrict__ T) {
+    size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (size_t)nb * q * pe * p) return;
+    const size_t row = t / p;
+    const int e = (int)(row % pe);
+    const int b = (int)(row / ((size_t)q * pe));
+    const double lm = cn[(size_t)b * pe + e] > 0.0 ? cn[(size_t)b * pe + e] : 1.0;
+    T[t] = (float)(z[t] / lm);
+}
+
+void warm_start_dataset(hipStream_t s, int nb, int p, int q, int pe, const double *c, const double *lam,
+                        const double *z, float *X, float *T, double *cn) {
+    launch_cnorm(s, nb, p, pe, c, cn);
+    size_t nx = (size_t)nb * q * pe * (p + 1), nt = (size_t)nb * q * pe * p;
+    hipLaunchKernelGGL(k_ws_inputs, dim3(cdiv(nx, 256)), dim3(256), 0, s, nb, p, q, pe, c, cn, lam, X);
+    hipLaunchKernelGGL(k_ws_targets, dim3(cdiv(nt, 256)), dim3(256), 0, s, nb, p, q, pe, cn, z, T);
+    UOI_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
 // Plain solver: one workgroup runs one whole solve with matrix-vector products
 // (the per-solve organisation of the paper's distributed ADMM, here without
 // row sharding).  z, u, v live in LDS; M and G are streamed every iteration.
@@ -252,7 +348,7 @@ __global__ __launch_bounds__(256) void k_admm_plain(int p, int pe, int R, const 
                                                     const double *__restrict__ C,
                                                     const double *__restrict__ lam,
                                                     const double *__restrict__ cn, double rho,
-                                                    double tol, int max_iter, int check_every,
+                                                    double alpha, double tol, int max_iter, int check_every,
                                                     double *__restrict__ zout,
                                                     double *__restrict__ uout,
                                                     int32_t *__restrict__ iters,
@@ -316,8 +412,9 @@ __global__ __launch_bounds__(256) void k_admm_plain(int p, int pe, int R, const 
         __syncthreads();
         nr = 0;
         for (int i = tid; i < p; i += 256, ++nr) {
-            double zn = soft_threshold(xr[nr] + u[i], thr);
-            double un = u[i] + xr[nr] - zn;
+            const double xh = alpha * xr[nr] + (1.0 - alpha) * z[i];
+            double zn = soft_threshold(xh + u[i], thr);
+            double un = u[i] + xh - zn;
             z[i] = zn;
             u[i] = un;
             v[i] = zn - un;
@@ -461,7 +558,7 @@ static int sweep(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T
             T *vout = (it & 1) ? va : vb;
             UOI_DISPATCH_FN(P.R, {
                 AdmmEpi<T, 1, FN> epi{h, z, u, vout, w.state, P.lam, P.p, P.R, P.pe, (T)P.rho,
-                                      (T)(1.0 / P.rho)};
+                                      (T)(1.0 / P.rho), (T)P.relax};
                 run_bgemm<T, 1, FN>(s, P.nb, P.p, P.R, M, vin, epi);
             });
             ++it;
@@ -508,7 +605,42 @@ void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, 
         UOI_HIP(hipMemcpyAsync(out.iters, neg.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, s));
         UOI_HIP(hipStreamSynchronize(s));
     }
-    if (!warm) {
+    out.warm_used = 0;
+    if (P.mlp) {
+        // network start for every (bootstrap, lambda); falls back to cold per solve
+        int nin = 0, nout = 0;
+        mlp_dims(P.mlp, &nin, &nout);
+        UOI_REQUIRE(P.pe == 1 && nin == P.p + 1 && nout == P.p,
+                    "warm-start network must have input p+1 and output p (LASSO only)");
+        const int n = P.nb * P.q;
+        float *Xs = mlp_input_buffer(P.mlp, n);
+        size_t nx = (size_t)n * (P.p + 1);
+        hipLaunchKernelGGL(k_ws_inputs, dim3(cdiv(nx, 256)), dim3(256), 0, s, P.nb, P.p, P.q, 1, P.C, w.cn,
+                           P.lam, Xs);
+        UOI_LAUNCH_CHECK();
+        mlp_forward(s, P.mlp, n, Xs);
+        hipLaunchKernelGGL(k_ws_z0, dim3(cdiv(nst, 256)), dim3(256), 0, s, P.nb, P.p, P.q,
+                           mlp_output(P.mlp), w.cn, out.z);
+        UOI_LAUNCH_CHECK();
+        double *Gz = w.v0 ? w.v0 : out.u;  // scratch of the state size
+        UOI_DISPATCH_FN(P.R, {
+            StoreEpi<double, 1, FN> epi{Gz, P.p, P.R};
+            run_bgemm<double, 1, FN>(s, P.nb, P.p, P.R, P.G, out.z, epi);
+        });
+        UOI_HIP(hipMemsetAsync(w.active, 0, sizeof(unsigned long long), s));
+        if (Gz == out.u) {
+            // plain solver: no spare state buffer; the completion reads Gz before writing u
+            UOI_REQUIRE(false, "warm start by network needs the batched solver");
+        }
+        hipLaunchKernelGGL(k_ws_finish, dim3(cdiv(P.nb * P.q, 64)), dim3(64), 0, s, P.nb, P.p, P.q, P.C, Gz,
+                           P.lam, P.rho, out.z, out.u, (unsigned long long *)w.active);
+        UOI_LAUNCH_CHECK();
+        unsigned long long used = 0;
+        UOI_HIP(hipMemcpyAsync(&used, w.active, sizeof(used), hipMemcpyDeviceToHost, s));
+        UOI_HIP(hipStreamSynchronize(s));
+        out.warm_used = (int64_t)used;
+        warm = true;
+    } else if (!warm) {
         UOI_HIP(hipMemsetAsync(out.z, 0, sizeof(double) * nst, s));
         UOI_HIP(hipMemsetAsync(out.u, 0, sizeof(double) * nst, s));
     }
@@ -523,8 +655,8 @@ void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, 
             UOI_HIP(hipEventRecord(e0, s));
         }
         hipLaunchKernelGGL(k_admm_plain, dim3(ns), dim3(256), lds, s, P.p, P.pe, P.R, w.M, w.h, P.G,
-                           P.C, P.lam, w.cn, P.rho, P.tol, P.max_iter, P.check_every, out.z, out.u,
-                           out.iters, out.kkt);
+                           P.C, P.lam, w.cn, P.rho, P.relax, P.tol, P.max_iter, P.check_every, out.z,
+                           out.u, out.iters, out.kkt);
         UOI_LAUNCH_CHECK();
         if (out.kstat) {
             UOI_HIP(hipEventRecord(e1, s));

@@ -188,6 +188,16 @@ void launch_matmul_f64(hipStream_t s, int nb, int p, int R, const double *A, con
                        double *Y);
 
 // ADMM state, batched FP64 / FP32 and plain.
+// training pairs of the warm-start network from solved problems (admm.hip)
+void warm_start_dataset(hipStream_t s, int nb, int p, int q, int pe, const double *c, const double *lam,
+                        const double *z, float *X, float *T, double *cn);
+
+// warm-start network (mlp.hip)
+void mlp_forward(hipStream_t s, uoi_mlp *M, int n, const float *X);
+float *mlp_input_buffer(uoi_mlp *M, int n);
+const float *mlp_output(const uoi_mlp *M);
+int mlp_dims(const uoi_mlp *M, int *n_in, int *n_out);
+
 struct AdmmProblem {
     int nb;              // bootstraps
     int p;               // features
@@ -201,6 +211,8 @@ struct AdmmProblem {
     double tol;
     int max_iter;
     int check_every;
+    uoi_mlp *mlp;        // warm start by network (LASSO: pe == 1), or nullptr
+    double relax;        // over-relaxation alpha (1 = plain scaled ADMM)
 };
 
 struct AdmmOut {
@@ -211,6 +223,7 @@ struct AdmmOut {
     int64_t unconverged;
     int max_iters;
     uoi_kstat *kstat;    // [UOI_KSTAT_N] accumulated when non-null (timing runs)
+    int64_t warm_used;   // solves started from the network
 };
 
 size_t admm_work_bytes(const AdmmProblem &P, int precision, int solver);

@@ -136,6 +136,27 @@ def lasso_toeplitz(seed: int = 0, *, n: int = 5000, p: int = 1000, k: int = 100,
                         f"lasso_toeplitz_n{n}_p{p}")
 
 
+def lasso_toeplitz_responses(seed: int, M: int, *, n: int = 5000, p: int = 1000, k: int = 100,
+                             rho_x: float = 0.5, snr: float = 5.0, q: int = 48, ratio: float = 1e-3):
+    """M independent (beta, noise) draws on one Toeplitz design: Y is n x M.
+
+    Same distribution per column as ``lasso_toeplitz`` (a fresh support of k
+    coefficients ~ N(0,1) and noise at the given SNR for every column); one
+    lambda grid for all columns, from the largest lambda_max among them."""
+    base = lasso_toeplitz(seed, n=n, p=p, k=k, rho_x=rho_x, snr=snr, q=q, ratio=ratio)
+    rng = np.random.default_rng(seed + 7919)
+    ii = np.arange(p)
+    S = np.power(rho_x, np.abs(ii[:, None] - ii[None, :]))
+    B = np.zeros((p, M))
+    for m in range(M):
+        idx = rng.choice(p, size=k, replace=False)
+        B[idx, m] = rng.standard_normal(k)
+    sig = np.sqrt(np.einsum("im,ij,jm->m", B, S, B) / snr)
+    Y = base.X @ B + rng.standard_normal((n, M)) * sig[None, :]
+    lam_max = float(np.max(np.abs(base.X.T @ Y))) / n
+    return base.X, np.ascontiguousarray(Y), B, _log_grid(lam_max, q, ratio)
+
+
 def var1(p: int, T: int, frac: float, radius: float, seed: int, *, burn: int = 500,
          q: int = 30, B1: int = 30, B2: int = 30, ratio: float = 1e-3) -> VarProblem:
     """VAR(1): x_t = A x_{t-1} + u_t, u_t ~ N(0, I), x_0 = 0, burn-in dropped."""

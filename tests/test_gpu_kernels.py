@@ -108,10 +108,11 @@ def _oracle_solutions(orc, G, c, lams):
     return np.array(out)
 
 
-@pytest.mark.parametrize("solver,precision", [("batched", "fp64"), ("plain", "fp64"),
-                                              ("batched", "mixed")])
+@pytest.mark.parametrize("solver,precision,relax", [("batched", "fp64", 1.0), ("plain", "fp64", 1.0),
+                                                    ("batched", "mixed", 1.0), ("batched", "fp64", 1.6),
+                                                    ("plain", "fp64", 1.7), ("batched", "mixed", 1.6)])
 @pytest.mark.parametrize("n,p,q", [(200, 50, 16), (400, 130, 9)])
-def test_admm_matches_oracle(api, orc, solver, precision, n, p, q):
+def test_admm_matches_oracle(api, orc, solver, precision, relax, n, p, q):
     pr = synth.lasso_random(n, p, 10, 5, q=q)
     Gs, cs = [], []
     for k in range(3):
@@ -120,7 +121,7 @@ def test_admm_matches_oracle(api, orc, solver, precision, n, p, q):
         cs.append(c)
     Gs, cs = np.array(Gs), np.array(cs)
     res = api.lasso_solve_batch(cuda(Gs), cuda(cs), pr.lambdas, kkt_tol=1e-10, solver=solver,
-                                precision=precision, max_iter=50000)
+                                precision=precision, max_iter=50000, relax=relax)
     z = res["z"].cpu().numpy()
     assert res["status"] == 0
     assert np.all(res["iters"].cpu().numpy() >= 0)

@@ -400,3 +400,49 @@ def test_var_p1_is_lasso_on_lagged_regression(orc):
     for lam in pr.lambdas:
         a, _ = orc.lasso_cd(G, Cm[:, 0], lam)
         assert a[0] == pytest.approx(_soft(c2[0], lam) / G2[0, 0], abs=1e-14)
+
+
+# ----------------------------------------------------------------------------
+# Warm-start network oracle
+# ----------------------------------------------------------------------------
+
+def test_mlp_gradients_match_finite_differences():
+    from oracle import mlp
+    rng = np.random.default_rng(0)
+    n_in, hid, n_out, n = 7, 5, 4, 6
+    ps = mlp.init_params(n_in, hid, n_out, seed=1)
+    ps[1] += 0.1; ps[3] += 0.1  # biases away from 0 so ReLU kinks are not hit
+    X = rng.standard_normal((n, n_in))
+    T = rng.standard_normal((n, n_out))
+    loss, grads = mlp.loss_and_grads(ps, X, T)
+    theta = mlp.flat(ps)
+    g = mlp.flat(grads)
+    h = 1e-6
+    for idx in rng.choice(theta.size, size=40, replace=False):
+        tp = theta.copy(); tp[idx] += h
+        tm = theta.copy(); tm[idx] -= h
+        lp, _ = mlp.loss_and_grads(mlp.unflat(tp, n_in, hid, n_out), X, T)
+        lm, _ = mlp.loss_and_grads(mlp.unflat(tm, n_in, hid, n_out), X, T)
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - g[idx]) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_bf16_rounding_is_nearest_even():
+    from oracle import mlp
+    # bf16 keeps 8 significand bits: 1 + 2^-8 is a tie between 1 and 1 + 2^-7 -> even (1)
+    assert mlp.bf16_round(1.0 + 2 ** -8) == 1.0
+    assert mlp.bf16_round(1.0 + 3 * 2 ** -8) == 1.0 + 2 ** -6
+    assert mlp.bf16_round(1.0 + 2 ** -7) == 1.0 + 2 ** -7
+    assert mlp.bf16_round(-3.0) == -3.0
+    x = np.random.default_rng(0).standard_normal(1000)
+    r = mlp.bf16_round(x)
+    assert np.all(np.abs(r - x) <= np.abs(x) * 2 ** -8)
+
+
+def test_adam_first_step_is_sign_scaled():
+    from oracle import mlp
+    # with m = v = 0, the bias-corrected first step is lr * g / (|g| + eps)
+    th = np.array([1.0, -2.0, 0.5])
+    g = np.array([0.3, -4.0, 1e-3])
+    new, m, v = mlp.adam_step(th, g, np.zeros(3), np.zeros(3), 1, 0.01)
+    np.testing.assert_allclose(new, th - 0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12)
