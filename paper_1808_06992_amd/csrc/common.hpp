@@ -174,6 +174,8 @@ void launch_expand_blocks(hipStream_t s, int nb, int nblk, int N, int L, const u
 void launch_gram_f64(hipStream_t s, int nb, int m, const int32_t *rows, const int32_t *mcount,
                      int p, const double *X, int ldx, int pe, const double *Y, int ldy,
                      double *G, double *C, double *ss = nullptr);
+// G[b][j][i] = G[b][i][j] for i > j (upper triangle from the lower one)
+void launch_symmetrize(hipStream_t s, int nb, int p, double *G);
 // sum of squares of Y columns over sampled rows / m:  ss[b*pe + e]
 void launch_colsq(hipStream_t s, int nb, int m, const int32_t *rows, const int32_t *mcount,
                   int pe, const double *Y, int ldy, double *ss);

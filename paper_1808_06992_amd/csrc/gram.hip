@@ -238,6 +238,12 @@ void launch_gram_f64(hipStream_t s, int nb, int m, const int32_t *rows, const in
     UOI_LAUNCH_CHECK();
 }
 
+void launch_symmetrize(hipStream_t s, int nb, int p, double *G) {
+    const int T32 = (int)cdiv(p, 32);
+    hipLaunchKernelGGL(k_symmetrize, dim3(T32, T32, nb), dim3(32, 8), 0, s, p, G);
+    UOI_LAUNCH_CHECK();
+}
+
 void launch_colsq(hipStream_t s, int nb, int m, const int32_t *rows, const int32_t *mcount,
                   int pe, const double *Y, int ldy, double *ss) {
     hipLaunchKernelGGL(k_colsq, dim3(cdiv(pe, 64), nb), dim3(256), 0, s, m, rows, mcount, pe, Y,

@@ -25,9 +25,9 @@ constexpr int SMALL = 88;  // whole-matrix in-LDS sweep up to this size (LDS <= 
 
 // Unblocked symmetric sweep of an n x n matrix held in LDS (row stride ld).
 // Leaves -A^{-1} in place.  256 threads; thread (ty, tx) = (tid/16, tid%16)
-// owns rows ty + 16a and columns tx + 16c (n <= 96).
+// owns rows ty + 16a and columns tx + 16c (n <= 16 MB).
+template <int MB>  // rows / columns per thread: n <= 16 * MB
 __device__ void lds_sweep(double *A, int n, int ld) {
-    constexpr int MB = 6;  // rows / columns per thread: n <= 96
     const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
     for (int k = 0; k < n; ++k) {
         const double pinv = 1.0 / A[k * ld + k];
@@ -80,7 +80,7 @@ __global__ __launch_bounds__(256) void k_inv_small(int p, const double *__restri
         A[e] = Gb[e] + (i == j ? rho : 0.0);
     }
     __syncthreads();
-    lds_sweep(A, p, p);
+    lds_sweep<6>(A, p, p);
     double *Mb = M + (size_t)b * p * p;
     for (int e = threadIdx.x; e < p * p; e += 256) Mb[e] = -A[e];
 }
@@ -113,7 +113,7 @@ __global__ __launch_bounds__(256) void k_pivot(int p, int k0, int kb, const doub
         if (i < kb && j < kb) S[i * LD + j] = Ab[(size_t)(k0 + i) * p + k0 + j];
     }
     __syncthreads();
-    lds_sweep(S, kb, LD);  // S = -Q
+    lds_sweep<4>(S, kb, LD);  // S = -Q
     double *Qb = Q + (size_t)b * NB * NB;
     for (int e = threadIdx.x; e < NB * NB; e += 256) {
         int i = e / NB, j = e % NB;
@@ -133,13 +133,20 @@ __global__ __launch_bounds__(256) void k_panel(int p, int k0, int kb, const doub
     const double *Ab = A + (size_t)b * p * p;
     const double *Qb = Q + (size_t)b * NB * NB;
     double *Ob = Old + (size_t)b * p * NB;
+    // Only the lower-triangle 128-tiles (and whole diagonal tiles) of A are kept up to
+    // date, so rows in a tile above the pivot's tile read A[i][K] as A[K][i].
+    const bool above = (i0 / 128) < (k0 / 128);
     for (int e = threadIdx.x; e < 64 * NB; e += 256) {
-        int r = e / NB, t = e % NB;
-        double v = (i0 + r < p && t < kb) ? Ab[(size_t)(i0 + r) * p + k0 + t] : 0.0;
+        int r, t;
+        if (above) { t = e / 64; r = e % 64; }   // coalesced along i
+        else { r = e / NB; t = e % NB; }          // coalesced along k
+        double v = 0.0;
+        if (i0 + r < p && t < kb)
+            v = above ? Ab[(size_t)(k0 + t) * p + i0 + r] : Ab[(size_t)(i0 + r) * p + k0 + t];
         As[t * LD + r] = v;
         if (i0 + r < p) Ob[(size_t)(i0 + r) * NB + t] = v;
-        Qs[r * LD + t] = Qb[e];  // (r, t) doubles as (row, column) of Q here
     }
+    for (int e = threadIdx.x; e < NB * NB; e += 256) Qs[(e / NB) * LD + e % NB] = Qb[e];
     __syncthreads();
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int wm = wid >> 1, wn = wid & 1;
@@ -167,7 +174,8 @@ __global__ __launch_bounds__(256) void k_panel(int p, int k0, int kb, const doub
             }
 }
 
-// (3) Rank-kb update of a 128x128 tile of A:
+// (3) Rank-kb update of a 128x128 tile of A (tiles on or below the diagonal only;
+// the sweep keeps A symmetric, the upper triangle is filled in at the end):
 //   i,j not in K: A_ij -= W_i . Old_j ;  i not in K, j in K: A_ij = W_i[j-k0]
 //   i in K, j not in K: A_ij = W_j[i-k0] ;  i, j in K: A_ij = -Q
 // W and Old are staged through LDS in quarters of the pivot index, transposed
@@ -180,9 +188,14 @@ __global__ __launch_bounds__(256, 2) void k_update(int p, int k0, int kb, double
     constexpr int QK = 16, LD = 128 + 1;
     __shared__ double Ws[QK * LD];
     __shared__ double Os[QK * LD];
-    int bx, by, b;
-    xcd_tile(bx, by, b);  // all tiles of one matrix on one XCD: W, Old stay in its L2
-    const int i0 = by * 128, j0 = bx * 128;
+    int tile, by0, b;
+    xcd_tile(tile, by0, b);  // all tiles of one matrix on one XCD: W, Old stay in its L2
+    // tile -> (ti, tj), tj <= ti: only the lower triangle (and whole diagonal tiles)
+    int ti = (int)((sqrt(8.0 * tile + 1.0) - 1.0) * 0.5);
+    while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
+    while (ti * (ti + 1) / 2 > tile) --ti;
+    const int tj = tile - ti * (ti + 1) / 2;
+    const int i0 = ti * 128, j0 = tj * 128;
     const double *Wb = W + (size_t)b * p * NB;
     const double *Ob = Old + (size_t)b * p * NB;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -268,14 +281,15 @@ void spd_inverse_f64(hipStream_t s, int nb, int p, const double *G, double rho, 
     size_t n = (size_t)nb * p * p;
     hipLaunchKernelGGL(k_shift_copy, dim3(cdiv(n, 256)), dim3(256), 0, s, n, p, G, rho, M);
     UOI_LAUNCH_CHECK();
+    const int T = (int)cdiv(p, 128);
     for (int k0 = 0; k0 < p; k0 += NB) {
         int kb = std::min(NB, p - k0);
         hipLaunchKernelGGL(k_pivot, dim3(nb), dim3(256), 0, s, p, k0, kb, M, Q);
         hipLaunchKernelGGL(k_panel, dim3(cdiv(p, 64), nb), dim3(256), 0, s, p, k0, kb, M, Q, W, Old);
-        hipLaunchKernelGGL(k_update, dim3(cdiv(p, 128), cdiv(p, 128), nb), dim3(256), 0, s, p, k0, kb,
-                           M, W, Old, Q);
+        hipLaunchKernelGGL(k_update, dim3(T * (T + 1) / 2, 1, nb), dim3(256), 0, s, p, k0, kb, M, W, Old, Q);
         UOI_LAUNCH_CHECK();
     }
+    launch_symmetrize(s, nb, p, M);
     hipLaunchKernelGGL(k_negate, dim3(cdiv(n, 256)), dim3(256), 0, s, n, M);
     UOI_LAUNCH_CHECK();
 }
