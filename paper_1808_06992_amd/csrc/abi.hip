@@ -219,7 +219,7 @@ static int lasso_fit(int n, int p, const double *X, const double *y, const uoi_o
     auto layout = [&](Arena &a, int32_t *&rows, double *&G, double *&c, double *&lam, double *&z,
                       double *&u, int32_t *&its, double *&kkt, uint8_t *&flag, int32_t *&tr,
                       int32_t *&ev, double *&GT, double *&CT, double *&GE, double *&CE, double *&sE,
-                      void *&admm_w, void *&est_w) {
+                      void *&admm_w, void *&est_w, void *&cw) {
         rows = a.take<int32_t>((size_t)B1 * n);
         G = a.take<double>((size_t)B1 * p * p);
         c = a.take<double>((size_t)B1 * p);
@@ -238,16 +238,17 @@ static int lasso_fit(int n, int p, const double *X, const double *y, const uoi_o
         sE = a.take<double>(B2);
         admm_w = a.take<char>(admm_work_bytes(P, o->precision, o->solver));
         est_w = a.take<char>(estim_work_bytes(E));
+        cw = a.take<char>(complement_work_bytes(n, p, 1));
     };
     int32_t *rows, *its, *tr, *ev;
     double *G, *c, *lam, *z, *u, *kkt, *GT, *CT, *GE, *CE, *sE;
     uint8_t *flag;
-    void *admm_w, *est_w;
-    layout(ar, rows, G, c, lam, z, u, its, kkt, flag, tr, ev, GT, CT, GE, CE, sE, admm_w, est_w);
+    void *admm_w, *est_w, *cw;
+    layout(ar, rows, G, c, lam, z, u, its, kkt, flag, tr, ev, GT, CT, GE, CE, sE, admm_w, est_w, cw);
     Arena A;
     A.cap = ar.off;
     A.base = (char *)pool_get(ar.off);
-    layout(A, rows, G, c, lam, z, u, its, kkt, flag, tr, ev, GT, CT, GE, CE, sE, admm_w, est_w);
+    layout(A, rows, G, c, lam, z, u, its, kkt, flag, tr, ev, GT, CT, GE, CE, sE, admm_w, est_w, cw);
 
     Timer tm(s, timing);
     tm.mark();
@@ -273,8 +274,11 @@ static int lasso_fit(int n, int p, const double *X, const double *y, const uoi_o
     // model estimation: splits, training / evaluation statistics, refits, union
     launch_split(s, o->seed, TAG_LASSO_SPLIT, B2, n, ntr, flag);
     launch_compact_rows(s, B2, n, flag, ntr, tr, ev);
-    launch_gram_f64(s, B2, ntr, tr, nullptr, p, X, p, 1, y, 1, GT, CT);
-    launch_gram_f64(s, B2, nev, ev, nullptr, p, X, p, 1, y, 1, GE, CE, sE);
+    // evaluation products directly; training products as their complement in the
+    // full-data product (the split partitions the rows), so the larger training
+    // side is never gathered
+    launch_gram_f64(s, B2, nev, ev, nullptr, p, X, p, 1, y, 1, GE, CE, sE, 1);
+    launch_train_from_eval(s, B2, n, p, X, p, 1, y, 1, GE, CE, ntr, nev, nullptr, nullptr, GT, CT, cw);
     tm.mark();
     E.GT = GT; E.CT = CT; E.GE = GE; E.CE = CE; E.sE = sE;
     estimate(s, E, est_w, beta_out, jstar_out, diag ? diag->losses : nullptr, timing ? sm + 6 : nullptr);
@@ -327,7 +331,7 @@ static int var_fit(int T, int p, int d, const double *series, int block_len, con
     auto layout = [&](Arena &a, int32_t *&rows, double *&G, double *&C, double *&lam, double *&z,
                       double *&u, int32_t *&its, double *&kkt, uint8_t *&flag, int32_t *&tr,
                       int32_t *&ev, int32_t *&ntr, int32_t *&nev, double *&GT, double *&CT,
-                      double *&GE, double *&CE, double *&sE, void *&admm_w, void *&est_w) {
+                      double *&GE, double *&CE, double *&sE, void *&admm_w, void *&est_w, void *&cw) {
         rows = a.take<int32_t>((size_t)B1 * N);
         G = a.take<double>((size_t)B1 * p * p);
         C = a.take<double>((size_t)B1 * p * pe);
@@ -348,17 +352,20 @@ static int var_fit(int T, int p, int d, const double *series, int block_len, con
         sE = a.take<double>((size_t)B2 * pe);
         admm_w = a.take<char>(admm_work_bytes(P, o->precision, o->solver));
         est_w = a.take<char>(estim_work_bytes(E));
+        cw = a.take<char>(complement_work_bytes(N, p, pe));
     };
     int32_t *rows, *its, *tr, *ev, *ntr, *nev;
     double *G, *C, *lam, *z, *u, *kkt, *GT, *CT, *GE, *CE, *sE;
     uint8_t *flag;
-    void *admm_w, *est_w;
+    void *admm_w, *est_w, *cw;
     Arena ar;
-    layout(ar, rows, G, C, lam, z, u, its, kkt, flag, tr, ev, ntr, nev, GT, CT, GE, CE, sE, admm_w, est_w);
+    layout(ar, rows, G, C, lam, z, u, its, kkt, flag, tr, ev, ntr, nev, GT, CT, GE, CE, sE, admm_w, est_w,
+           cw);
     Arena A;
     A.cap = ar.off;
     A.base = (char *)pool_get(ar.off);
-    layout(A, rows, G, C, lam, z, u, its, kkt, flag, tr, ev, ntr, nev, GT, CT, GE, CE, sE, admm_w, est_w);
+    layout(A, rows, G, C, lam, z, u, its, kkt, flag, tr, ev, ntr, nev, GT, CT, GE, CE, sE, admm_w, est_w,
+           cw);
 
     const double *Xd = series, *Yd = series + p;  // regression row r: x = series[r], y = series[r+1]
     Timer tm(s, timing);
@@ -383,9 +390,9 @@ static int var_fit(int T, int p, int d, const double *series, int block_len, con
     tm.mark();
     launch_split(s, o->seed, TAG_VAR_SPLIT, B2, nblk, nbt, flag);
     launch_expand_blocks(s, B2, nblk, N, L, flag, tr, ev, ntr, nev);
-    launch_gram_f64(s, B2, N, tr, ntr, p, Xd, p, pe, Yd, p, GT, CT);
-    launch_gram_f64(s, B2, N, ev, nev, p, Xd, p, pe, Yd, p, GE, CE);
+    launch_gram_f64(s, B2, N, ev, nev, p, Xd, p, pe, Yd, p, GE, CE, nullptr, 1);
     launch_colsq(s, B2, N, ev, nev, pe, Yd, p, sE);
+    launch_train_from_eval(s, B2, N, p, Xd, p, pe, Yd, p, GE, CE, 0, 0, ntr, nev, GT, CT, cw);
     tm.mark();
     E.GT = GT; E.CT = CT; E.GE = GE; E.CE = CE; E.sE = sE;
     estimate(s, E, est_w, A_out, jstar_out, diag ? diag->losses : nullptr, timing ? sm + 6 : nullptr);

@@ -173,12 +173,22 @@ void launch_expand_blocks(hipStream_t s, int nb, int nblk, int N, int L, const u
 // and ss != nullptr, ss[b][e] = sum_r Y[r][e]^2 / m comes out of the same product.
 void launch_gram_f64(hipStream_t s, int nb, int m, const int32_t *rows, const int32_t *mcount,
                      int p, const double *X, int ldx, int pe, const double *Y, int ldy,
-                     double *G, double *C, double *ss = nullptr);
+                     double *G, double *C, double *ss = nullptr, int role = 0);
 // G[b][j][i] = G[b][i][j] for i > j (upper triangle from the lower one)
 void launch_symmetrize(hipStream_t s, int nb, int p, double *G);
 // sum of squares of Y columns over sampled rows / m:  ss[b*pe + e]
 void launch_colsq(hipStream_t s, int nb, int m, const int32_t *rows, const int32_t *mcount,
                   int pe, const double *Y, int ldy, double *ss);
+// Training-set statistics of nb disjoint training/evaluation splits of the n
+// rows, from the evaluation statistics and one full-data product:
+// nt_b G_T,b = X'X - ne_b G_E,b (likewise for C).  Counts are the scalars
+// nt_c/ne_c, or per split from device arrays nt/ne when those are non-null.
+// complement_work_bytes sizes the scratch the full-data product needs.
+size_t complement_work_bytes(int n, int p, int pe);
+void launch_train_from_eval(hipStream_t s, int nb, int n, int p, const double *X, int ldx, int pe,
+                            const double *Y, int ldy, const double *GE, const double *CE,
+                            int nt_c, int ne_c, const int32_t *nt, const int32_t *ne, double *GT,
+                            double *CT, void *work);
 
 // Batched inverse of G + rho I by blocked Gauss-Jordan sweeps (writes M).
 void spd_inverse_f64(hipStream_t s, int nb, int p, const double *G, double rho, double *M,

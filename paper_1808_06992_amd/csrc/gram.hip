@@ -48,6 +48,9 @@ __device__ __forceinline__ double aug_col(const GramArgs &g, size_t r, int j) {
     return 0.0;
 }
 
+// ROLE only names the instance (0: selection products of the bootstrap samples,
+// 1: estimation products), so kernel profiles keep the two apart.
+template <int ROLE>
 __global__ __launch_bounds__(256, 2) void k_gram_f64(GramArgs g) {
     __shared__ double As[GK][GT];
     __shared__ double Bs[GK][GT];
@@ -166,7 +169,10 @@ __global__ __launch_bounds__(256, 2) void k_gram_f64(GramArgs g) {
                 if (isC) {
                     if (i < g.p && j < g.pe) g.C[(gb + i) * g.pe + j] = v;
                 } else if (j <= i && i < naug) {
-                    if (i < g.p) g.G[(gb + i) * g.p + j] = v;        // design block (lower)
+                    if (i < g.p) {                                   // design block, both halves
+                        g.G[(gb + i) * g.p + j] = v;
+                        if (j < i) g.G[(gb + j) * g.p + i] = v;
+                    }
                     else if (j < g.p) g.C[(gb + j) * g.pa + (i - g.p)] = v;  // X'y block
                     else if (i == j && g.ss) g.ss[(size_t)b * g.pa + (i - g.p)] = v;  // y'y diagonal
                 }
@@ -221,7 +227,7 @@ __global__ __launch_bounds__(256) void k_colsq(int m, const int32_t *__restrict_
 
 void launch_gram_f64(hipStream_t s, int nb, int m, const int32_t *rows, const int32_t *mcount,
                      int p, const double *X, int ldx, int pe, const double *Y, int ldy,
-                     double *G, double *C, double *ss) {
+                     double *G, double *C, double *ss, int role) {
     GramArgs g{};
     g.m = m; g.rows = rows; g.mcount = mcount; g.p = p; g.X = X; g.ldx = ldx;
     g.Y = Y; g.ldy = ldy; g.G = G; g.C = C; g.ss = ss;
@@ -231,10 +237,10 @@ void launch_gram_f64(hipStream_t s, int nb, int m, const int32_t *rows, const in
     g.T = (int)cdiv(p + g.pa, GT);
     g.Tc = g.pe > 0 ? (int)cdiv(g.pe, GT) : 0;
     const int tiles = g.T * (g.T + 1) / 2 + (int)cdiv(p, GT) * g.Tc;
-    hipLaunchKernelGGL(k_gram_f64, dim3(tiles, nb), dim3(256), 0, s, g);
-    UOI_LAUNCH_CHECK();
-    const int T32 = (int)cdiv(p, 32);
-    hipLaunchKernelGGL(k_symmetrize, dim3(T32, T32, nb), dim3(32, 8), 0, s, p, G);
+    if (role == 0)
+        hipLaunchKernelGGL(k_gram_f64<0>, dim3(tiles, nb), dim3(256), 0, s, g);
+    else
+        hipLaunchKernelGGL(k_gram_f64<1>, dim3(tiles, nb), dim3(256), 0, s, g);
     UOI_LAUNCH_CHECK();
 }
 
@@ -248,6 +254,104 @@ void launch_colsq(hipStream_t s, int nb, int m, const int32_t *rows, const int32
                   int pe, const double *Y, int ldy, double *ss) {
     hipLaunchKernelGGL(k_colsq, dim3(cdiv(pe, 64), nb), dim3(256), 0, s, m, rows, mcount, pe, Y,
                        ldy, ss);
+    UOI_LAUNCH_CHECK();
+}
+
+// --------------------------------------------------------------------------
+// Full-data sums split over contiguous row slices (one Gram launch with a
+// slice per batch entry keeps the chip busy when only one product is needed),
+// and training statistics as their complement to the evaluation statistics.
+
+// Slice k holds rows k*mp .. min((k+1)*mp, n) - 1.
+__global__ void k_row_slices(int n, int mp, int32_t *__restrict__ rows, int32_t *__restrict__ cnt) {
+    const int k = blockIdx.y;
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = max(0, min(mp, n - k * mp));
+    if (r == 0) cnt[k] = c;
+    if (r < c) rows[(size_t)k * mp + r] = k * mp + r;
+}
+
+// S[i] = sum_k cnt_k P[k][i]  (un-normalised sums of the slices)
+__global__ void k_sum_slices(size_t len, int ns, const double *__restrict__ P,
+                             const int32_t *__restrict__ cnt, double *__restrict__ S) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < len;
+         i += (size_t)gridDim.x * blockDim.x) {
+        double a = 0.0;
+        for (int k = 0; k < ns; ++k) a += (double)cnt[k] * P[(size_t)k * len + i];
+        S[i] = a;
+    }
+}
+
+// T[b][i] = (S[i] - ne_b E[b][i]) / nt_b
+__global__ void k_complement(size_t len, const double *__restrict__ S, const double *__restrict__ E,
+                             int nt_c, int ne_c, const int32_t *__restrict__ nt,
+                             const int32_t *__restrict__ ne, double *__restrict__ T) {
+    const int b = blockIdx.y;
+    const double fe = ne ? (double)ne[b] : (double)ne_c;
+    const double inv = 1.0 / (nt ? (double)nt[b] : (double)nt_c);
+    const double *Eb = E + (size_t)b * len;
+    double *Tb = T + (size_t)b * len;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < len;
+         i += (size_t)gridDim.x * blockDim.x)
+        Tb[i] = (S[i] - fe * Eb[i]) * inv;
+}
+
+namespace {
+struct SliceShape {
+    int ns, mp;
+};
+SliceShape slice_shape(int n, int p, int pe) {
+    const bool aug = pe > 0 && pe < AUG_MAX;
+    const int T = (int)cdiv(p + (aug ? pe : 0), GT);
+    const int Tc = aug || pe == 0 ? 0 : (int)cdiv(pe, GT);
+    const int tiles = T * (T + 1) / 2 + (int)cdiv(p, GT) * Tc;
+    int ns = (int)std::min<int64_t>(32, cdiv(768, tiles));
+    ns = std::max(1, std::min(ns, n / 64));
+    const int mp = (int)cdiv(n, ns);
+    return {(int)cdiv(n, mp), mp};
+}
+}  // namespace
+
+size_t complement_work_bytes(int n, int p, int pe) {
+    const SliceShape sh = slice_shape(n, p, pe);
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    return al(sizeof(int32_t) * (size_t)sh.ns * sh.mp) + al(sizeof(int32_t) * sh.ns) +
+           al(sizeof(double) * (size_t)sh.ns * p * (p + pe)) + al(sizeof(double) * (size_t)p * (p + pe));
+}
+
+void launch_train_from_eval(hipStream_t s, int nb, int n, int p, const double *X, int ldx, int pe,
+                            const double *Y, int ldy, const double *GE, const double *CE,
+                            int nt_c, int ne_c, const int32_t *nt, const int32_t *ne, double *GT,
+                            double *CT, void *work) {
+    const SliceShape sh = slice_shape(n, p, pe);
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    char *w = (char *)work;
+    int32_t *rows = (int32_t *)w;
+    w += al(sizeof(int32_t) * (size_t)sh.ns * sh.mp);
+    int32_t *cnt = (int32_t *)w;
+    w += al(sizeof(int32_t) * sh.ns);
+    double *Gp = (double *)w;
+    double *Cp = Gp + (size_t)sh.ns * p * p;
+    w += al(sizeof(double) * (size_t)sh.ns * p * (p + pe));
+    double *SG = (double *)w;
+    double *SC = SG + (size_t)p * p;
+
+    hipLaunchKernelGGL(k_row_slices, dim3(cdiv(sh.mp, 256), sh.ns), dim3(256), 0, s, n, sh.mp, rows, cnt);
+    UOI_LAUNCH_CHECK();
+    launch_gram_f64(s, sh.ns, sh.mp, rows, cnt, p, X, ldx, pe, Y, ldy, Gp, Cp, nullptr, 1);
+    const size_t lg = (size_t)p * p, lc = (size_t)p * pe;
+    const int nbk = 1024;
+    hipLaunchKernelGGL(k_sum_slices, dim3((unsigned)std::min<size_t>(cdiv(lg, 256), nbk)), dim3(256), 0,
+                       s, lg, sh.ns, Gp, cnt, SG);
+    UOI_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_sum_slices, dim3((unsigned)std::min<size_t>(cdiv(lc, 256), nbk)), dim3(256), 0,
+                       s, lc, sh.ns, Cp, cnt, SC);
+    UOI_LAUNCH_CHECK();
+    const int gx = (int)std::min<size_t>(cdiv(lg, 256), 128);
+    hipLaunchKernelGGL(k_complement, dim3(gx, nb), dim3(256), 0, s, lg, SG, GE, nt_c, ne_c, nt, ne, GT);
+    UOI_LAUNCH_CHECK();
+    const int gc = (int)std::min<size_t>(cdiv(lc, 256), 128);
+    hipLaunchKernelGGL(k_complement, dim3(gc, nb), dim3(256), 0, s, lc, SC, CE, nt_c, ne_c, nt, ne, CT);
     UOI_LAUNCH_CHECK();
 }
 

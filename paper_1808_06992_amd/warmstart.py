@@ -17,7 +17,19 @@ import torch
 from . import _lib as api
 from . import synth
 
-__all__ = ["problem_pairs", "make_training_set", "train", "evaluate"]
+__all__ = ["init_theta", "problem_pairs", "make_training_set", "train", "fit_network", "evaluate"]
+
+
+def init_theta(n_in: int, hidden: int, n_out: int, seed: int = 0) -> torch.Tensor:
+    """He-uniform weights, zero biases, in the flat order W1 b1 W2 b2 W3 b3
+    (W stored [out][in]) that uoi_mlp_set_params takes."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fi, fo in ((n_in, hidden), (hidden, hidden), (hidden, n_out)):
+        lim = np.sqrt(6.0 / fi)
+        parts.append(rng.uniform(-lim, lim, size=fo * fi))
+        parts.append(np.zeros(fo))
+    return torch.as_tensor(np.concatenate(parts).astype(np.float32), device="cuda")
 
 
 def problem_pairs(pr, seed: int, B1: int, kkt_tol: float = 1e-8):
@@ -73,6 +85,18 @@ def train(net: "api.MLP", X: torch.Tensor, T: torch.Tensor, *, epochs: int = 10,
         if log:
             log(f"epoch {ep}: loss {hist[-1]:.4e}")
     return hist
+
+
+def fit_network(seeds, *, B1: int = 8, M: int = 64, hidden: int = 512, epochs: int = 30,
+                batch: int = 512, lr: float = 2e-3, init_seed: int = 7, log=None, **gen_kw):
+    """Training set from the given design seeds, then a freshly initialised
+    network trained on it.  Returns (net, loss history, number of training solves)."""
+    X, T = make_training_set(seeds, B1=B1, M=M, **gen_kw)
+    p = T.shape[1]
+    net = api.MLP(p + 1, hidden, p)
+    net.set_params(init_theta(p + 1, hidden, p, init_seed))
+    hist = train(net, X, T, epochs=epochs, batch=batch, lr=lr, log=log)
+    return net, hist, int(X.shape[0])
 
 
 def evaluate(net, seeds, gen=synth.lasso_toeplitz, B1: int = 48, B2: int = 48, kkt_tol: float = 1e-6,
