@@ -184,11 +184,19 @@ __global__ void k_cnorm(int p, int pe, const double *__restrict__ C, double *__r
 }
 
 // After a KKT evaluation: freeze solves that meet the tolerance.
-// state: 0 active, 1 converged, 2 parked (met park_tol, waits for float64).
+// state: 0 active, 1 converged, 2 parked (waits for float64): a float32 solve is
+// parked when it meets park_tol, or when it is within stall_tol but its KKT
+// residual fell by less than kStallRatio since the previous check (it has
+// reached what float32 arithmetic resolves).  kkt[] holds the previous value
+// (initialised to a huge number).
+constexpr double kStallRatio = 0.7;
+constexpr double kParkFactor = 3.0;
+constexpr double kStallFactor = 30.0;
 __global__ void k_freeze(int nb, int R, int pe, const double *__restrict__ vmax,
-                         const double *__restrict__ cn, double tol, double park_tol, int it,
-                         uint8_t *__restrict__ state, int32_t *__restrict__ iters,
-                         double *__restrict__ kkt, int *__restrict__ active) {
+                         const double *__restrict__ cn, double tol, double park_tol,
+                         double stall_tol, int it, uint8_t *__restrict__ state,
+                         int32_t *__restrict__ iters, double *__restrict__ kkt,
+                         int *__restrict__ active) {
     // active[0] = all solves still active, active[1 + b] = those of bootstrap b
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     bool act = false;
@@ -197,11 +205,12 @@ __global__ void k_freeze(int nb, int R, int pe, const double *__restrict__ vmax,
         if (state[s] == 0) {
             double c = cn[(size_t)b * pe + r % pe];
             double rel = c > 0.0 ? vmax[s] / c : vmax[s];
+            const double prev = kkt[s];
             kkt[s] = rel;
             if (rel <= tol) {
                 state[s] = 1;
                 iters[s] = it;
-            } else if (rel <= park_tol) {
+            } else if (rel <= park_tol || (rel <= stall_tol && rel > kStallRatio * prev)) {
                 state[s] = 2;
             } else {
                 act = true;
@@ -495,7 +504,7 @@ size_t admm_work_bytes(const AdmmProblem &P, int precision, int solver) {
 // number of solves still active.
 template <typename T>
 static int check(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T *z, bool only_active,
-                 double park_tol, int it, AdmmOut &out, std::vector<int> &act_b) {
+                 double park_tol, double stall_tol, int it, AdmmOut &out, std::vector<int> &act_b) {
     UOI_HIP(hipMemsetAsync(w.vmax, 0, sizeof(double) * (size_t)P.nb * P.R, s));
     UOI_HIP(hipMemsetAsync(w.active, 0, sizeof(int) * (1 + P.nb), s));
     if (std::is_same<T, double>::value) {
@@ -517,7 +526,7 @@ static int check(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T
     }
     int ns = P.nb * P.R;
     hipLaunchKernelGGL(k_freeze, dim3(cdiv(ns, 256)), dim3(256), 0, s, P.nb, P.R, P.pe, w.vmax, w.cn,
-                       P.tol, park_tol, it, w.state, out.iters, out.kkt, w.active);
+                       P.tol, park_tol, stall_tol, it, w.state, out.iters, out.kkt, w.active);
     UOI_LAUNCH_CHECK();
     act_b.resize(1 + P.nb);
     UOI_HIP(hipMemcpyAsync(act_b.data(), w.active, sizeof(int) * (1 + P.nb), hipMemcpyDeviceToHost, s));
@@ -527,9 +536,10 @@ static int check(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T
 
 template <typename T>
 static int sweep(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T *M, const T *h,
-                 T *z, T *u, T *va, T *vb, int &it, int it_cap, double park_tol, AdmmOut &out) {
+                 T *z, T *u, T *va, T *vb, int &it, int it_cap, double park_tol, double stall_tol,
+                 AdmmOut &out) {
     std::vector<int> act_b;
-    int active = check<T>(s, P, w, z, true, park_tol, it, out, act_b);
+    int active = check<T>(s, P, w, z, true, park_tol, stall_tol, it, out, act_b);
     uoi_kstat *ks = out.kstat ? &out.kstat[std::is_same<T, double>::value ? UOI_KSTAT_ADMM64
                                                                            : UOI_KSTAT_ADMM32]
                               : nullptr;
@@ -564,7 +574,7 @@ static int sweep(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T
             ++it;
         }
         if (ks) UOI_HIP(hipEventRecord(e1, s));
-        active = check<T>(s, P, w, z, true, park_tol, it, out, act_b);
+        active = check<T>(s, P, w, z, true, park_tol, stall_tol, it, out, act_b);
         if (ks) {
             float ms = 0.f;
             UOI_HIP(hipEventElapsedTime(&ms, e0, e1));
@@ -600,6 +610,7 @@ void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, 
     if (stage_ms) UOI_HIP(hipEventRecord(ev[1], s));
 
     UOI_HIP(hipMemsetAsync(w.state, 0, ns, s));
+    UOI_HIP(hipMemsetAsync(out.kkt, 0x7f, sizeof(double) * ns, s));  // "previous" KKT: huge
     {
         std::vector<int32_t> neg(ns, -1);
         UOI_HIP(hipMemcpyAsync(out.iters, neg.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, s));
@@ -682,10 +693,12 @@ void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, 
         hipLaunchKernelGGL(k_refresh_v<double>, dim3(cdiv(nst, 256)), dim3(256), 0, s, nst, out.z,
                            out.u, w.v0, w.v1);
         UOI_LAUNCH_CHECK();
-        active = sweep<double>(s, P, w, w.M, w.h, out.z, out.u, w.v0, w.v1, it, P.max_iter, P.tol, out);
+        active = sweep<double>(s, P, w, w.M, w.h, out.z, out.u, w.v0, w.v1, it, P.max_iter, P.tol, 0.0,
+                               out);
     } else {
         // float32 phase: operator and state in float32, KKT in float64; solves that
-        // reach 10x the tolerance are parked and finished in float64.
+        // reach kParkFactor x the tolerance, or stall within kStallFactor x the
+        // tolerance, are parked and finished in float64.
         size_t np2 = (size_t)P.nb * P.p * P.p, nh = (size_t)P.nb * P.p * P.pe;
         hipLaunchKernelGGL(k_f64_to_f32, dim3(cdiv(np2, 256)), dim3(256), 0, s, np2, w.M, w.M32);
         hipLaunchKernelGGL(k_f64_to_f32, dim3(cdiv(nh, 256)), dim3(256), 0, s, nh, w.h, w.h32);
@@ -694,9 +707,8 @@ void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, 
         hipLaunchKernelGGL(k_refresh_v<float>, dim3(cdiv(nst, 256)), dim3(256), 0, s, nst, w.z32,
                            w.u32, w.w0, w.w1);
         UOI_LAUNCH_CHECK();
-        const double park = P.tol * 10.0;
-        active = sweep<float>(s, P, w, w.M32, w.h32, w.z32, w.u32, w.w0, w.w1, it, P.max_iter, park,
-                              out);
+        active = sweep<float>(s, P, w, w.M32, w.h32, w.z32, w.u32, w.w0, w.w1, it, P.max_iter,
+                              P.tol * kParkFactor, P.tol * kStallFactor, out);
         // widen the state and finish parked / active solves in float64
         hipLaunchKernelGGL(k_f32_to_f64, dim3(cdiv(nst, 256)), dim3(256), 0, s, nst, w.z32, out.z);
         hipLaunchKernelGGL(k_f32_to_f64, dim3(cdiv(nst, 256)), dim3(256), 0, s, nst, w.u32, out.u);
@@ -706,7 +718,7 @@ void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, 
         UOI_LAUNCH_CHECK();
         int it64 = it;
         active = sweep<double>(s, P, w, w.M, w.h, out.z, out.u, w.v0, w.v1, it64, P.max_iter + it,
-                               P.tol, out);
+                               P.tol, 0.0, out);
         it = it64;
     }
     if (stage_ms) {

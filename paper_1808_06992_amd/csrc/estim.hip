@@ -9,6 +9,10 @@
 //   - |S| <= kSmall: one workgroup per (split, support) gathers G_T[S,S] into
 //     LDS, factors it by Cholesky and solves (supports of uneven size run side by
 //     side, each workgroup sized by its own support);
+//   - kSmall < |S| <= kMid: one workgroup per (split, support) runs a
+//     left-looking blocked Cholesky, reading G_T[S,S] straight from G_T and
+//     keeping the factor in global scratch (L2-resident), with c_T[S] carried as
+//     an extra row so that the forward solve comes out of the factorization;
 //   - larger supports: conjugate gradients on the masked operator, batched over
 //     all (split, support) pairs of a split so that every iteration is one MFMA
 //     product with G_T (the same kernel as the ADMM x-update).
@@ -24,6 +28,9 @@ namespace uoi {
 
 namespace {
 constexpr int kSmall = 80;   // in-LDS Cholesky up to this support size
+constexpr int kMid = 256;    // blocked Cholesky with the factor in global scratch up to this size
+constexpr int kPW = 16;      // panel width of the blocked Cholesky
+constexpr size_t kMidScratch = (size_t)256 << 20;  // bytes of factor storage per launch
 constexpr double kCgTol = 1e-13;
 constexpr int kCgMaxIter = 4000;
 }
@@ -149,6 +156,138 @@ __global__ __launch_bounds__(256) void k_ols_small(int p, int pe, int R, int W,
                          sE[(size_t)k * pe + e]);
     if (threadIdx.x == 0) {
         loss[(size_t)k * R + r] = L;
+        if (fail) atomicOr(bad, 1);
+    }
+}
+
+// Mid-size supports.  Grid: one workgroup per listed system (split k, support r).
+// The factor of the bordered matrix [G_T[S,S]; c_T[S]'] is stored column-major
+// with leading dimension s+1 (column t holds rows t..s; row s is L^{-1} c).
+__global__ __launch_bounds__(256) void k_ols_mid(int p, int pe, int R, int W,
+                                                 const uint64_t *__restrict__ supp,
+                                                 const int2 *__restrict__ sys,
+                                                 const size_t *__restrict__ off,
+                                                 double *__restrict__ Lbase,
+                                                 const double *__restrict__ GT,
+                                                 const double *__restrict__ CT,
+                                                 const double *__restrict__ GE,
+                                                 const double *__restrict__ CE,
+                                                 const double *__restrict__ sE,
+                                                 double *__restrict__ Fit, double *__restrict__ loss,
+                                                 int *__restrict__ bad) {
+    constexpr int LDP = kPW + 1;
+    __shared__ int idx[kMid];
+    __shared__ double Pn[(kMid + 1) * LDP];  // panel rows kb..s, kPW columns
+    __shared__ double Lp[64][LDP];           // staged rows kb..kb+kPW of the factor
+    __shared__ double xv[kMid + 1];
+    __shared__ double red[8][33];
+    __shared__ int fail;
+    const int tid = threadIdx.x;
+    const int k = sys[blockIdx.x].x, r = sys[blockIdx.x].y;
+    const int e = r % pe;
+    const int s = support_members(supp + (size_t)r * W, W, idx);  // kSmall < s <= kMid (host)
+    const int ld = s + 1;
+    double *L = Lbase + off[blockIdx.x];
+    const double *GTb = GT + (size_t)k * p * p;
+    const double *CTb = CT + (size_t)k * p * pe;
+    if (tid == 0) fail = 0;
+    for (int kb = 0; kb < s; kb += kPW) {
+        const int nbk = min(kPW, s - kb);
+        const int m = s + 1 - kb;  // panel rows kb..s (row s is the right-hand side)
+        for (int q = tid; q < m * kPW; q += 256) {
+            const int c = q / m, i = q % m;
+            double v = 0.0;
+            if (c < nbk) {
+                const int gi = kb + i, gc = idx[kb + c];
+                v = gi < s ? GTb[(size_t)gc * p + idx[gi]] : CTb[(size_t)gc * pe + e];
+            }
+            Pn[i * LDP + c] = v;
+        }
+        __syncthreads();
+        // left-looking: subtract the contribution of the factored columns 0..kb
+        for (int t0 = 0; t0 < kb; t0 += 64) {
+            const int nt = min(64, kb - t0);
+            for (int q = tid; q < 64 * kPW; q += 256) {
+                const int t = q / kPW, c = q % kPW;
+                Lp[t][c] = (t < nt && c < nbk) ? L[(size_t)(t0 + t) * ld + kb + c] : 0.0;
+            }
+            __syncthreads();
+            for (int i = tid; i < m; i += 256) {
+                double acc[kPW];
+#pragma unroll
+                for (int c = 0; c < kPW; ++c) acc[c] = Pn[i * LDP + c];
+                for (int t = 0; t < nt; ++t) {
+                    const double a = L[(size_t)(t0 + t) * ld + kb + i];
+#pragma unroll
+                    for (int c = 0; c < kPW; ++c) acc[c] -= a * Lp[t][c];
+                }
+#pragma unroll
+                for (int c = 0; c < kPW; ++c) Pn[i * LDP + c] = acc[c];
+            }
+            __syncthreads();
+        }
+        // factor the panel in LDS
+        for (int c = 0; c < nbk; ++c) {
+            if (tid == 0) {
+                double d = Pn[c * LDP + c];
+                if (!(d > 0.0)) { fail = 1; d = 1.0; }
+                Pn[c * LDP + c] = sqrt(d);
+            }
+            __syncthreads();
+            const double dc = Pn[c * LDP + c];
+            for (int i = c + 1 + tid; i < m; i += 256) Pn[i * LDP + c] /= dc;
+            __syncthreads();
+            for (int i = c + 1 + tid; i < m; i += 256) {
+                const double lic = Pn[i * LDP + c];
+                for (int c2 = c + 1; c2 < nbk && c2 <= i; ++c2) Pn[i * LDP + c2] -= lic * Pn[c2 * LDP + c];
+            }
+            __syncthreads();
+        }
+        for (int q = tid; q < m * nbk; q += 256) {
+            const int c = q / m, i = q % m;
+            if (i >= c) L[(size_t)(kb + c) * ld + kb + i] = Pn[i * LDP + c];
+        }
+        __syncthreads();
+    }
+    // backward solve L' x = y with y = row s of the factor, in blocks of 32 from the end
+    for (int t = tid; t < s; t += 256) xv[t] = L[(size_t)t * ld + s];
+    __syncthreads();
+    for (int t1 = s; t1 > 0; t1 -= 32) {
+        const int t0 = max(0, t1 - 32);
+        {   // xv[t] -= sum_{i >= t1} L[i][t] x_i for t in [t0, t1)
+            const int tt = tid & 31, g = tid >> 5;
+            const int t = t0 + tt;
+            double part = 0.0;
+            if (t < t1)
+                for (int i = t1 + g; i < s; i += 8) part += L[(size_t)t * ld + i] * xv[i];
+            red[g][tt] = part;
+        }
+        __syncthreads();
+        if (tid < 64) {  // one wave: the diagonal block, sequentially from its end
+            const int tt = tid & 31;
+            if (tid < 32 && t0 + tt < t1) {
+                double sacc = 0.0;
+                for (int g = 0; g < 8; ++g) sacc += red[g][tt];
+                xv[t0 + tt] -= sacc;
+            }
+            for (int t = t1 - 1; t >= t0; --t) {
+                // x_t = (x_t - sum_{t < i < t1} L[i][t] x_i) / L[t][t]
+                const int i = t + 1 + tid;
+                double v = (tid < 32 && i < t1) ? L[(size_t)t * ld + i] * xv[i] : 0.0;
+                v = wave_sum(v);
+                if (tid == 0) xv[t] = (xv[t] - v) / L[(size_t)t * ld + t];
+            }
+        }
+        __syncthreads();
+    }
+    double *F = Fit + ((size_t)k * R + r) * p;
+    for (int i = tid; i < p; i += 256) F[i] = 0.0;
+    __syncthreads();
+    for (int a = tid; a < s; a += 256) F[idx[a]] = xv[a];
+    double Lo = eval_loss(s, idx, xv, GE + (size_t)k * p * p, CE + (size_t)k * p * pe, p, pe, e,
+                          sE[(size_t)k * pe + e]);
+    if (tid == 0) {
+        loss[(size_t)k * R + r] = Lo;
         if (fail) atomicOr(bad, 1);
     }
 }
@@ -356,7 +495,15 @@ __global__ void k_average(int nb, int p, int pe, int R, const double *__restrict
 
 // ---------------------------------------------------------------------------
 namespace {
+size_t mid_scratch_doubles(const EstimProblem &E) {
+    const int sm = std::min(E.p, kMid);
+    const size_t worst = (size_t)E.nb * E.R * (size_t)(sm + 1) * sm;
+    return std::min(worst, kMidScratch / sizeof(double));
+}
 struct EstimWork {
+    int2 *sys;
+    size_t *off;
+    double *Lmid;
     int32_t *cnt, *Lidx;
     double *Fit, *loss, *Lq;
     double *X, *Rv, *P, *AP, *rr, *rr0, *rrn, *pAp;
@@ -365,7 +512,7 @@ struct EstimWork {
 };
 EstimWork carve(const EstimProblem &E, int nL, Arena &ar) {
     EstimWork w{};
-    w.cnt = ar.take<int32_t>(E.R);
+    w.cnt = ar.take<int32_t>(E.R);  // first: the popcounts are written here before the carve
     w.Lidx = ar.take<int32_t>(std::max(nL, 1));
     w.Fit = ar.take<double>((size_t)E.nb * E.R * E.p);
     w.loss = ar.take<double>((size_t)E.nb * E.R);
@@ -382,6 +529,10 @@ EstimWork carve(const EstimProblem &E, int nL, Arena &ar) {
     w.pAp = ar.take<double>(ns);
     w.state = ar.take<uint8_t>(ns);
     w.flags = ar.take<int>(2);
+    const size_t nsys = (size_t)E.nb * E.R;
+    w.sys = ar.take<int2>(nsys);
+    w.off = ar.take<size_t>(nsys);
+    w.Lmid = E.p > kSmall ? ar.take<double>(mid_scratch_doubles(E)) : nullptr;
     return w;
 }
 }  // namespace
@@ -407,10 +558,11 @@ void estimate(hipStream_t s, const EstimProblem &E, void *work, double *beta_out
     std::vector<int32_t> hc(E.R);
     UOI_HIP(hipMemcpyAsync(hc.data(), cnt, sizeof(int32_t) * E.R, hipMemcpyDeviceToHost, s));
     UOI_HIP(hipStreamSynchronize(s));
-    std::vector<int32_t> lidx;
+    std::vector<int32_t> lidx, mids;
     int smax = 0;
     for (int r = 0; r < E.R; ++r) {
-        if (hc[r] > kSmall) lidx.push_back(r);
+        if (hc[r] > kMid) lidx.push_back(r);
+        else if (hc[r] > kSmall) mids.push_back(r);
         else smax = std::max(smax, (int)hc[r]);
     }
     const int nL = (int)lidx.size();
@@ -431,6 +583,37 @@ void estimate(hipStream_t s, const EstimProblem &E, void *work, double *beta_out
     hipLaunchKernelGGL(k_ols_small, dim3(E.R, E.nb), dim3(256), lds, s, E.p, E.pe, E.R, W, E.supp,
                        w.cnt, E.GT, E.CT, E.GE, E.CE, E.sE, w.Fit, w.loss, w.flags);
     UOI_LAUNCH_CHECK();
+    // mid-size supports: blocked Cholesky per (split, support), in chunks that fit
+    // the factor scratch
+    if (!mids.empty()) {
+        const size_t cap = mid_scratch_doubles(E);
+        std::vector<int2> sys;
+        std::vector<size_t> off;
+        size_t used = 0;
+        auto flush = [&]() {
+            if (sys.empty()) return;
+            UOI_HIP(hipMemcpyAsync(w.sys, sys.data(), sizeof(int2) * sys.size(), hipMemcpyHostToDevice, s));
+            UOI_HIP(hipMemcpyAsync(w.off, off.data(), sizeof(size_t) * off.size(), hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(k_ols_mid, dim3((unsigned)sys.size()), dim3(256), 0, s, E.p, E.pe, E.R, W,
+                               E.supp, w.sys, w.off, w.Lmid, E.GT, E.CT, E.GE, E.CE, E.sE, w.Fit, w.loss,
+                               w.flags);
+            UOI_LAUNCH_CHECK();
+            // the host lists are reused only after the copies above have completed
+            UOI_HIP(hipStreamSynchronize(s));
+            sys.clear();
+            off.clear();
+            used = 0;
+        };
+        for (int k = 0; k < E.nb; ++k)
+            for (int r : mids) {
+                const size_t need = (size_t)(hc[r] + 1) * hc[r];
+                if (used + need > cap) flush();
+                sys.push_back(make_int2(k, r));
+                off.push_back(used);
+                used += need;
+            }
+        flush();
+    }
     // large supports by batched conjugate gradients
     if (nL) {
         size_t ns = (size_t)E.nb * nL;

@@ -10,10 +10,13 @@
 // and sweeping every block leaves -A^{-1}.  Pivots are Schur complements of
 // an SPD matrix, so no pivoting is needed.
 //
-// Per block step: (1) one workgroup per matrix sweeps the kb x kb pivot block in
-// LDS (Q = A_KK^{-1}); (2) a row-parallel MFMA kernel forms W = A_:K Q and keeps
-// the old panel A_:K; (3) a tiled MFMA kernel applies the rank-kb update to the
-// whole matrix.
+// Per 64-wide block step: (1) one workgroup per matrix sweeps the pivot block
+// in registers (Q = A_KK^{-1}); (2) a row-parallel MFMA kernel forms W = A_:K Q
+// and keeps the old panel A_:K, both stored pivot-index-major; (3) an MFMA kernel
+// applies the rank-64 update to the 64x64 tiles on and below the diagonal (the
+// sweep keeps A symmetric).  The first step reads G and adds rho on the
+// diagonal, so no shifted copy is made; a final pass negates and fills the upper
+// triangle.
 #include "common.hpp"
 
 namespace uoi {
@@ -85,69 +88,91 @@ __global__ __launch_bounds__(256) void k_inv_small(int p, const double *__restri
     for (int e = threadIdx.x; e < p * p; e += 256) Mb[e] = -A[e];
 }
 
-// M = G + rho I (the matrix that the blocked sweep works on in place)
-__global__ void k_shift_copy(size_t n, int p, const double *__restrict__ G, double rho,
-                             double *__restrict__ M) {
-    size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < n) {
-        size_t w = e % ((size_t)p * p);
-        int i = (int)(w / p), j = (int)(w % p);
-        M[e] = G[e] + (i == j ? rho : 0.0);
-    }
-}
-
-__global__ void k_negate(size_t n, double *__restrict__ M) {
-    size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < n) M[e] = -M[e];
-}
-
-// (1) Q = A_KK^{-1} for pivot block [k0, k0+kb) (one workgroup per matrix).
-__global__ __launch_bounds__(256) void k_pivot(int p, int k0, int kb, const double *__restrict__ A,
-                                               double *__restrict__ Q) {
-    constexpr int LD = NB + 1;
-    __shared__ double S[NB * LD];
+// (1) Q = A_KK^{-1} of the pivot block [k0, k0+kb), one workgroup per matrix.
+// Thread (ty, tx) = (tid / 64, tid % 64) keeps rows ty + 4a (a < 16) of column
+// tx in registers for all 64 steps (the block is padded with the identity
+// beyond kb, which leaves the kb x kb part unchanged); step k publishes the old
+// pivot row and column through LDS, double-buffered by step parity so that one
+// barrier per step suffices.  LDS reads are broadcasts or unit-stride.
+// The first block step reads G and adds the shift rho on the diagonal.
+__global__ __launch_bounds__(256) void k_pivot(int p, int k0, int kb, const double *__restrict__ src,
+                                               double shift, double *__restrict__ Q) {
+    __shared__ double rowb[2][NB], colb[2][NB];
     const int b = blockIdx.x;
-    const double *Ab = A + (size_t)b * p * p;
-    for (int e = threadIdx.x; e < NB * NB; e += 256) {
-        int i = e / NB, j = e % NB;
-        if (i < kb && j < kb) S[i * LD + j] = Ab[(size_t)(k0 + i) * p + k0 + j];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const double *Ab = src + (size_t)b * p * p;
+    double v[16];
+#pragma unroll
+    for (int a = 0; a < 16; ++a) {
+        const int i = ty + 4 * a;
+        v[a] = (i < kb && tx < kb) ? Ab[(size_t)(k0 + i) * p + k0 + tx] + (i == tx ? shift : 0.0)
+                                   : (i == tx ? 1.0 : 0.0);
     }
-    __syncthreads();
-    lds_sweep<4>(S, kb, LD);  // S = -Q
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        const int buf = k & 1;
+        if (ty == (k & 3)) rowb[buf][tx] = v[k >> 2];
+        if (tx == k) {
+#pragma unroll
+            for (int a = 0; a < 16; ++a) colb[buf][ty + 4 * a] = v[a];
+        }
+        __syncthreads();
+        const double pinv = 1.0 / rowb[buf][k];
+        const double rk = rowb[buf][tx];
+#pragma unroll
+        for (int a = 0; a < 16; ++a) {
+            const int i = ty + 4 * a;
+            const double aik = colb[buf][i] * pinv;
+            double nv;
+            if (i != k && tx != k) nv = v[a] - aik * rk;   // A_ij - A_ik A_kj / A_kk
+            else if (i != k) nv = aik;                     // column k
+            else if (tx != k) nv = rk * pinv;              // row k
+            else nv = -pinv;                               // pivot
+            v[a] = nv;
+        }
+    }
     double *Qb = Q + (size_t)b * NB * NB;
-    for (int e = threadIdx.x; e < NB * NB; e += 256) {
-        int i = e / NB, j = e % NB;
-        Qb[e] = (i < kb && j < kb) ? -S[i * LD + j] : 0.0;  // stored NB x NB, zero padded
+#pragma unroll
+    for (int a = 0; a < 16; ++a) {
+        const int i = ty + 4 * a;
+        Qb[i * NB + tx] = (i < kb && tx < kb) ? -v[a] : 0.0;  // zero padded
     }
 }
 
-// (2) Panel for rows [i0, i0+64): Old = A[i, K], W = A[i, K] Q on MFMA.
-__global__ __launch_bounds__(256) void k_panel(int p, int k0, int kb, const double *__restrict__ A,
-                                               const double *__restrict__ Q, double *__restrict__ W,
-                                               double *__restrict__ Old) {
+// (2) Panel for rows [i0, i0+64): Old = A[i, K] and W = A[i, K] Q (MFMA), both
+// stored pivot-index-major (Wt[t][i], Ot[t][i], t < NB) so that the update reads
+// them as unit-stride MFMA operands.  Only the lower-triangle 64-tiles of A are
+// current, so rows above the pivot block read A[i][K] as A[K][i].
+__global__ __launch_bounds__(256) void k_panel(int p, int k0, int kb, const double *__restrict__ src,
+                                               double shift, const double *__restrict__ Q,
+                                               double *__restrict__ Wt, double *__restrict__ Ot) {
     constexpr int LD = 64 + 1;
-    __shared__ double As[NB * LD];  // As[t][r] = A[i0 + r][k0 + t]
+    __shared__ double As[NB * LD];  // As[t][r] = A[i0 + r][k0 + t]; later W staged as [c][r]
     __shared__ double Qs[NB * LD];  // Qs[t][c] = Q[t][c]
     const int b = blockIdx.y;
     const int i0 = blockIdx.x * 64;
-    const double *Ab = A + (size_t)b * p * p;
+    const double *Ab = src + (size_t)b * p * p;
     const double *Qb = Q + (size_t)b * NB * NB;
-    double *Ob = Old + (size_t)b * p * NB;
-    // Only the lower-triangle 128-tiles (and whole diagonal tiles) of A are kept up to
-    // date, so rows in a tile above the pivot's tile read A[i][K] as A[K][i].
-    const bool above = (i0 / 128) < (k0 / 128);
+    double *Wb = Wt + (size_t)b * p * NB;
+    double *Ob = Ot + (size_t)b * p * NB;
+    const bool above = i0 < k0;
     for (int e = threadIdx.x; e < 64 * NB; e += 256) {
         int r, t;
         if (above) { t = e / 64; r = e % 64; }   // coalesced along i
         else { r = e / NB; t = e % NB; }          // coalesced along k
         double v = 0.0;
-        if (i0 + r < p && t < kb)
+        if (i0 + r < p && t < kb) {
             v = above ? Ab[(size_t)(k0 + t) * p + i0 + r] : Ab[(size_t)(i0 + r) * p + k0 + t];
+            if (i0 + r == k0 + t) v += shift;
+        }
         As[t * LD + r] = v;
-        if (i0 + r < p) Ob[(size_t)(i0 + r) * NB + t] = v;
     }
     for (int e = threadIdx.x; e < NB * NB; e += 256) Qs[(e / NB) * LD + e % NB] = Qb[e];
     __syncthreads();
+    for (int e = threadIdx.x; e < 64 * NB; e += 256) {
+        const int t = e / 64, r = e % 64;
+        if (i0 + r < p) Ob[(size_t)t * p + i0 + r] = As[t * LD + r];
+    }
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int wm = wid >> 1, wn = wid & 1;
     const int lr = lane & 15, lk = lane >> 4;
@@ -165,100 +190,115 @@ __global__ __launch_bounds__(256) void k_panel(int p, int k0, int kb, const doub
         acc[1][0] = mfma16x16x4(a1, b0, acc[1][0]);
         acc[1][1] = mfma16x16x4(a1, b1, acc[1][1]);
     }
-    double *Wb = W + (size_t)b * p * NB;
+    __syncthreads();  // As is reused to stage W as [c][r]
     for (int fm = 0; fm < 2; ++fm)
         for (int fn = 0; fn < 2; ++fn)
             for (int t = 0; t < 4; ++t) {
                 int r = wm * 32 + fm * 16 + mfma_row(0.0, lk, t), c = wn * 32 + fn * 16 + lr;
-                if (i0 + r < p) Wb[(size_t)(i0 + r) * NB + c] = acc[fm][fn][t];
+                As[c * LD + r] = acc[fm][fn][t];
             }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * NB; e += 256) {
+        const int c = e / 64, r = e % 64;
+        if (i0 + r < p) Wb[(size_t)c * p + i0 + r] = As[c * LD + r];
+    }
 }
 
-// (3) Rank-kb update of a 128x128 tile of A (tiles on or below the diagonal only;
-// the sweep keeps A symmetric, the upper triangle is filled in at the end):
+// (3) Rank-kb update of one 64x64 tile on or below the diagonal:
 //   i,j not in K: A_ij -= W_i . Old_j ;  i not in K, j in K: A_ij = W_i[j-k0]
 //   i in K, j not in K: A_ij = W_j[i-k0] ;  i, j in K: A_ij = -Q
-// W and Old are staged through LDS in quarters of the pivot index, transposed
-// (pivot-index-major, padded rows) so that the MFMA operand reads are conflict
-// free; each wave owns a 64x64 quadrant as 4x4 MFMA blocks.
-__global__ __launch_bounds__(256, 2) void k_update(int p, int k0, int kb, double *__restrict__ A,
-                                                   const double *__restrict__ W,
-                                                   const double *__restrict__ Old,
-                                                   const double *__restrict__ Q) {
-    constexpr int QK = 16, LD = 128 + 1;
-    __shared__ double Ws[QK * LD];
-    __shared__ double Os[QK * LD];
+// Each wave owns a 32x32 quadrant (2x2 MFMA blocks).  The tile's old values are
+// requested first; the operands W_i[t] and Old_j[t] are read straight from the
+// pivot-index-major panels (unit stride along i, L2-resident), with no LDS and no
+// barrier.  Step 0 reads G (+ rho on the diagonal) and writes M.
+__global__ __launch_bounds__(256) void k_update(int p, int k0, int kb, const double *__restrict__ src,
+                                                double shift, double *__restrict__ dst,
+                                                const double *__restrict__ Wt,
+                                                const double *__restrict__ Ot,
+                                                const double *__restrict__ Q) {
     int tile, by0, b;
-    xcd_tile(tile, by0, b);  // all tiles of one matrix on one XCD: W, Old stay in its L2
-    // tile -> (ti, tj), tj <= ti: only the lower triangle (and whole diagonal tiles)
+    xcd_tile(tile, by0, b);  // all tiles of one matrix on one XCD: the panels stay in its L2
     int ti = (int)((sqrt(8.0 * tile + 1.0) - 1.0) * 0.5);
     while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
     while (ti * (ti + 1) / 2 > tile) --ti;
     const int tj = tile - ti * (ti + 1) / 2;
-    const int i0 = ti * 128, j0 = tj * 128;
-    const double *Wb = W + (size_t)b * p * NB;
-    const double *Ob = Old + (size_t)b * p * NB;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int wm = wid >> 1, wn = wid & 1;
     const int lr = lane & 15, lk = lane >> 4;
-    dx4 acc[4][4];
+    const int ib = ti * 64 + wm * 32, jb = tj * 64 + wn * 32;  // quadrant origin
+    const double *Ab = src + (size_t)b * p * p;
+    double old[2][2][4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int fm = 0; fm < 2; ++fm)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[a][c] = dx4{0, 0, 0, 0};
-    const int nq = (kb + QK - 1) / QK;
-    for (int h = 0; h < nq; ++h) {
-        for (int e = threadIdx.x; e < 128 * QK; e += 256) {
-            int r = e / QK, t = e % QK;
-            Ws[t * LD + r] = (i0 + r < p) ? Wb[(size_t)(i0 + r) * NB + h * QK + t] : 0.0;
-            Os[t * LD + r] = (j0 + r < p) ? Ob[(size_t)(j0 + r) * NB + h * QK + t] : 0.0;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int s = 0; s < QK / 4; ++s) {
-            double av[4], bv[4];
-#pragma unroll
-            for (int a = 0; a < 4; ++a) av[a] = Ws[(4 * s + lk) * LD + wm * 64 + 16 * a + lr];
-#pragma unroll
-            for (int a = 0; a < 4; ++a) bv[a] = Os[(4 * s + lk) * LD + wn * 64 + 16 * a + lr];
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int c = 0; c < 4; ++c) acc[a][c] = mfma16x16x4(av[a], bv[c], acc[a][c]);
-        }
-        __syncthreads();
-    }
-    double *Ab = A + (size_t)b * p * p;
-    const double *Qb = Q + (size_t)b * NB * NB;
-    const bool plain = !(i0 < k0 + kb && i0 + 128 > k0) && !(j0 < k0 + kb && j0 + 128 > k0);
-#pragma unroll
-    for (int fm = 0; fm < 4; ++fm) {
-        // read-modify-write one 16-row band: loads first, then stores
-        double old[4][4];
-#pragma unroll
-        for (int fn = 0; fn < 4; ++fn)
+        for (int fn = 0; fn < 2; ++fn)
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                const int i = i0 + wm * 64 + fm * 16 + mfma_row(0.0, lk, t);
-                const int j = j0 + wn * 64 + fn * 16 + lr;
-                old[fn][t] = (i < p && j < p) ? Ab[(size_t)i * p + j] : 0.0;
+                const int i = ib + fm * 16 + mfma_row(0.0, lk, t), j = jb + fn * 16 + lr;
+                old[fm][fn][t] = (i < p && j < p) ? Ab[(size_t)i * p + j] + (i == j ? shift : 0.0) : 0.0;
             }
+    const double *Wb = Wt + (size_t)b * p * NB;
+    const double *Ob = Ot + (size_t)b * p * NB;
+    const int ia0 = ib + lr, ia1 = ib + 16 + lr, jb0 = jb + lr, jb1 = jb + 16 + lr;
+    dx4 acc[2][2];
 #pragma unroll
-        for (int fn = 0; fn < 4; ++fn)
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) acc[a][c] = dx4{0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < NB / 4; ++s) {
+        const int t = 4 * s + lk;  // rows t >= kb of the panels are zero
+        const size_t o = (size_t)t * p;
+        const double a0 = ia0 < p ? Wb[o + ia0] : 0.0, a1 = ia1 < p ? Wb[o + ia1] : 0.0;
+        const double b0 = jb0 < p ? Ob[o + jb0] : 0.0, b1 = jb1 < p ? Ob[o + jb1] : 0.0;
+        acc[0][0] = mfma16x16x4(a0, b0, acc[0][0]);
+        acc[0][1] = mfma16x16x4(a0, b1, acc[0][1]);
+        acc[1][0] = mfma16x16x4(a1, b0, acc[1][0]);
+        acc[1][1] = mfma16x16x4(a1, b1, acc[1][1]);
+    }
+    double *Db = dst + (size_t)b * p * p;
+    const double *Qb = Q + (size_t)b * NB * NB;
+    const int kt = k0 / 64;
+    const bool plain = ti != kt && tj != kt;
+#pragma unroll
+    for (int fm = 0; fm < 2; ++fm)
+#pragma unroll
+        for (int fn = 0; fn < 2; ++fn)
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                const int i = i0 + wm * 64 + fm * 16 + mfma_row(0.0, lk, t);
-                const int j = j0 + wn * 64 + fn * 16 + lr;
+                const int i = ib + fm * 16 + mfma_row(0.0, lk, t), j = jb + fn * 16 + lr;
                 if (i >= p || j >= p) continue;
-                double v = old[fn][t] - acc[fm][fn][t];             // A_ij - A_iK Q A_Kj
+                double v = old[fm][fn][t] - acc[fm][fn][t];
                 if (!plain) {
                     const bool iK = i >= k0 && i < k0 + kb, jK = j >= k0 && j < k0 + kb;
-                    if (iK && jK) v = -Qb[(i - k0) * NB + (j - k0)];      // -Q
-                    else if (jK) v = Wb[(size_t)i * NB + (j - k0)];       // A_iK Q
-                    else if (iK) v = Wb[(size_t)j * NB + (i - k0)];       // Q A_Kj = (A_jK Q)'
+                    if (iK && jK) v = -Qb[(i - k0) * NB + (j - k0)];        // -Q
+                    else if (jK) v = Wb[(size_t)(j - k0) * p + i];          // A_iK Q
+                    else if (iK) v = Wb[(size_t)(i - k0) * p + j];          // Q A_Kj = (A_jK Q)'
                 }
-                Ab[(size_t)i * p + j] = v;
+                Db[(size_t)i * p + j] = v;
             }
+}
+
+// (4) M = -(swept matrix), with the upper triangle filled from the lower one:
+// 32x32 tiles on or below the diagonal are read through LDS and written to
+// both positions (diagonal tiles from their lower triangle only).
+__global__ void k_symneg(int p, double *__restrict__ M) {
+    __shared__ double t[32][33];
+    const int b = blockIdx.z;
+    const int bi = blockIdx.y, bj = blockIdx.x;
+    if (bj > bi) return;
+    double *Mb = M + (size_t)b * p * p;
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    for (int r = ty; r < 32; r += 8) {
+        const int i = bi * 32 + r, j = bj * 32 + tx;
+        if (i < p && j < p) t[r][tx] = Mb[(size_t)i * p + j];
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int i = bi * 32 + r, j = bj * 32 + tx;      // lower position
+        if (i < p && j < p && (bi > bj || r >= tx)) Mb[(size_t)i * p + j] = -t[r][tx];
+        const int i2 = bj * 32 + r, j2 = bi * 32 + tx;    // upper position (i2, j2) = (j, i)
+        if (i2 < p && j2 < p && (bi > bj || tx > r)) Mb[(size_t)i2 * p + j2] = -t[tx][r];
     }
 }
 
@@ -276,21 +316,22 @@ void spd_inverse_f64(hipStream_t s, int nb, int p, const double *G, double rho, 
         return;
     }
     double *Q = work;
-    double *W = Q + (size_t)nb * NB * NB;
-    double *Old = W + (size_t)nb * p * NB;
-    size_t n = (size_t)nb * p * p;
-    hipLaunchKernelGGL(k_shift_copy, dim3(cdiv(n, 256)), dim3(256), 0, s, n, p, G, rho, M);
-    UOI_LAUNCH_CHECK();
-    const int T = (int)cdiv(p, 128);
+    double *Wt = Q + (size_t)nb * NB * NB;
+    double *Ot = Wt + (size_t)nb * p * NB;
+    const int T = (int)cdiv(p, 64);
     for (int k0 = 0; k0 < p; k0 += NB) {
-        int kb = std::min(NB, p - k0);
-        hipLaunchKernelGGL(k_pivot, dim3(nb), dim3(256), 0, s, p, k0, kb, M, Q);
-        hipLaunchKernelGGL(k_panel, dim3(cdiv(p, 64), nb), dim3(256), 0, s, p, k0, kb, M, Q, W, Old);
-        hipLaunchKernelGGL(k_update, dim3(T * (T + 1) / 2, 1, nb), dim3(256), 0, s, p, k0, kb, M, W, Old, Q);
+        const int kb = std::min(NB, p - k0);
+        // the first step reads G + rho I and writes every lower tile of M
+        const double *src = k0 == 0 ? G : M;
+        const double sh = k0 == 0 ? rho : 0.0;
+        hipLaunchKernelGGL(k_pivot, dim3(nb), dim3(256), 0, s, p, k0, kb, src, sh, Q);
+        hipLaunchKernelGGL(k_panel, dim3(T, nb), dim3(256), 0, s, p, k0, kb, src, sh, Q, Wt, Ot);
+        hipLaunchKernelGGL(k_update, dim3(T * (T + 1) / 2, 1, nb), dim3(256), 0, s, p, k0, kb, src, sh, M,
+                           Wt, Ot, Q);
         UOI_LAUNCH_CHECK();
     }
-    launch_symmetrize(s, nb, p, M);
-    hipLaunchKernelGGL(k_negate, dim3(cdiv(n, 256)), dim3(256), 0, s, n, M);
+    const int T32 = (int)cdiv(p, 32);
+    hipLaunchKernelGGL(k_symneg, dim3(T32, T32, nb), dim3(32, 8), 0, s, p, M);
     UOI_LAUNCH_CHECK();
 }
 

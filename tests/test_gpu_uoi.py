@@ -103,6 +103,37 @@ def test_uoi_lasso_ragged_sizes(api, orc):
         check_jstar(ref["losses"], ref["jstar"], out["jstar"].cpu().numpy())
 
 
+def test_uoi_lasso_all_refit_paths(api, orc):
+    """Dense coefficients make the intersection supports span every refit route:
+    in-LDS Cholesky (|S| <= 80), blocked Cholesky with the factor in global
+    scratch (80 < |S| <= 256) and conjugate gradients (|S| > 256); every
+    lambda's loss is compared, so each route is checked against the oracle's QR."""
+    pr = synth.lasso_random(700, 320, 320, 5, noise=0.1, q=10, B1=3, B2=3)
+    seed = 5
+    ref = orc.uoi_lasso(pr.X, pr.y, pr.lambdas, pr.B1, pr.B2, seed, keep_selection=True)
+    assert ref["status"] == 0
+    out = api.lasso_fit(cuda(pr.X), cuda(pr.y), pr.lambdas, pr.B1, pr.B2, seed, kkt_tol=1e-10)
+    assert out["status"] == 0
+    p = pr.X.shape[1]
+    got = words_to_bool(out["supports"].cpu().numpy(), p)
+    want = words_to_bool(ref["supports"], p)
+    sizes = want.sum(1)
+    assert sizes.min() <= 80 and np.any((sizes > 80) & (sizes <= 256)) and sizes.max() > 256
+    dec = lasso_decided(orc, pr, seed, ref["sel_beta"])
+    assert np.array_equal(got[dec], want[dec])
+    same = np.all(got == want, axis=1)       # lambdas whose supports agree bit for bit
+    for lo, hi in ((0, 80), (81, 256), (257, p)):
+        assert np.any(same & (sizes >= lo) & (sizes <= hi)), (lo, hi, sizes, same)
+    lg = out["losses"].cpu().numpy()
+    np.testing.assert_allclose(lg[:, same], ref["losses"][:, same], rtol=1e-9)
+    if same.all():
+        jg = out["jstar"].cpu().numpy()
+        check_jstar(ref["losses"], ref["jstar"], jg)
+        if np.array_equal(jg, ref["jstar"]):
+            b = out["beta"].cpu().numpy()
+            assert np.abs(b - ref["beta"]).max() <= 1e-6 * np.abs(ref["beta"]).max()
+
+
 def test_uoi_var_small(api, orc):
     pr = synth.var1(12, 600, 0.15, 0.8, 4, burn=50, q=6, B1=4, B2=4)
     seed = 3
