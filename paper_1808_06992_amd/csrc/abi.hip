@@ -141,6 +141,16 @@ static void transpose(hipStream_t s, int nb, int p, int R, const double *a, doub
     UOI_LAUNCH_CHECK();
 }
 
+// Host sum of n device int32 values (synchronises the stream; timing mode only).
+static long long sum_device_ints(hipStream_t s, const int32_t *d, int n) {
+    std::vector<int32_t> h(n);
+    UOI_HIP(hipMemcpyAsync(h.data(), d, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+    UOI_HIP(hipStreamSynchronize(s));
+    long long t = 0;
+    for (int v : h) t += v;
+    return t;
+}
+
 // Times one launch sequence on the stream and adds it to a kernel-stat slot.
 struct KernelTimer {
     hipStream_t s;
@@ -152,9 +162,15 @@ struct KernelTimer {
         UOI_HIP(hipEventCreate(&e1));
         UOI_HIP(hipEventRecord(e0, s));
     }
+    bool stopped = false;
+    void stop() {  // end of the timed launches (done() may follow after other work)
+        if (!k || stopped) return;
+        UOI_HIP(hipEventRecord(e1, s));
+        stopped = true;
+    }
     void done(double bytes, double flops) {
         if (!k) return;
-        UOI_HIP(hipEventRecord(e1, s));
+        stop();
         UOI_HIP(hipEventSynchronize(e1));
         float ms = 0.f;
         UOI_HIP(hipEventElapsedTime(&ms, e0, e1));
@@ -220,7 +236,7 @@ static int lasso_fit(int n, int p, const double *X, const double *y, const uoi_o
                       double *&u, int32_t *&its, double *&kkt, uint8_t *&flag, int32_t *&tr,
                       int32_t *&ev, double *&GT, double *&CT, double *&GE, double *&CE, double *&sE,
                       void *&admm_w, void *&est_w, void *&cw) {
-        rows = a.take<int32_t>((size_t)B1 * n);
+        rows = a.take<int32_t>((size_t)4 * B1 * n + B1);  // draws, counts, distinct rows, weights, sizes
         G = a.take<double>((size_t)B1 * p * p);
         c = a.take<double>((size_t)B1 * p);
         lam = a.take<double>(q);
@@ -256,10 +272,18 @@ static int lasso_fit(int n, int p, const double *X, const double *y, const uoi_o
     // model selection: bootstrap rows, Gram, ADMM sweep, supports
     launch_boot_rows(s, o->seed, TAG_LASSO_BOOT, B1, n, rows);
     {
+        // the Gram of a bootstrap sample runs over its distinct rows weighted by
+        // their multiplicities (about 63% of n rows) and divides by n
+        int32_t *cntb = rows + (size_t)B1 * n, *drow = cntb + (size_t)B1 * n, *dw = drow + (size_t)B1 * n;
+        int32_t *nd = dw + (size_t)B1 * n;
+        launch_distinct_rows(s, B1, n, n, rows, cntb, drow, dw, nd);
         KernelTimer kt(s, timing && diag ? &diag->kstat[UOI_KSTAT_GRAM] : nullptr);
-        launch_gram_f64(s, B1, n, rows, nullptr, p, X, p, 1, y, 1, G, c);
-        kt.done((double)B1 * ((double)n * (p + 1) * 8 + (double)p * (p + 1) * 8),
-                (double)B1 * ((double)n * p * (p + 1) + 2.0 * n * p));
+        launch_gram_f64_weighted(s, B1, n, drow, dw, nd, n, p, X, p, 1, y, 1, G, c);
+        kt.stop();
+        if (timing && diag) {
+            const double md = (double)sum_device_ints(s, nd, B1);  // rows actually processed
+            kt.done(md * (p + 1) * 8 + (double)B1 * p * (p + 1) * 8, md * p * (p + 1) + 2.0 * md * p);
+        }
     }
     tm.mark();
     P.G = G;
@@ -332,7 +356,7 @@ static int var_fit(int T, int p, int d, const double *series, int block_len, con
                       double *&u, int32_t *&its, double *&kkt, uint8_t *&flag, int32_t *&tr,
                       int32_t *&ev, int32_t *&ntr, int32_t *&nev, double *&GT, double *&CT,
                       double *&GE, double *&CE, double *&sE, void *&admm_w, void *&est_w, void *&cw) {
-        rows = a.take<int32_t>((size_t)B1 * N);
+        rows = a.take<int32_t>((size_t)4 * B1 * N + B1);  // draws, counts, distinct rows, weights, sizes
         G = a.take<double>((size_t)B1 * p * p);
         C = a.take<double>((size_t)B1 * p * pe);
         lam = a.take<double>(q);
@@ -373,10 +397,18 @@ static int var_fit(int T, int p, int d, const double *series, int block_len, con
     UOI_HIP(hipMemcpyAsync(lam, o->lambdas, sizeof(double) * q, hipMemcpyHostToDevice, s));
     launch_var_boot_rows(s, o->seed, B1, N, L, rows);
     {
+        // distinct regression rows of each block-bootstrap sample, weighted by
+        // their multiplicities
+        int32_t *cntb = rows + (size_t)B1 * N, *drow = cntb + (size_t)B1 * N, *dw = drow + (size_t)B1 * N;
+        int32_t *nd = dw + (size_t)B1 * N;
+        launch_distinct_rows(s, B1, N, N, rows, cntb, drow, dw, nd);
         KernelTimer kt(s, timing && diag ? &diag->kstat[UOI_KSTAT_GRAM] : nullptr);
-        launch_gram_f64(s, B1, N, rows, nullptr, p, Xd, p, pe, Yd, p, G, C);
-        kt.done((double)B1 * ((double)N * (p + pe) * 8 + (double)p * (p + pe) * 8),
-                (double)B1 * ((double)N * p * (p + 1) + 2.0 * N * p * pe));
+        launch_gram_f64_weighted(s, B1, N, drow, dw, nd, N, p, Xd, p, pe, Yd, p, G, C);
+        kt.stop();
+        if (timing && diag) {
+            const double md = (double)sum_device_ints(s, nd, B1);
+            kt.done(md * (p + pe) * 8 + (double)B1 * p * (p + pe) * 8, md * p * (p + 1) + 2.0 * md * p * pe);
+        }
     }
     tm.mark();
     P.G = G;

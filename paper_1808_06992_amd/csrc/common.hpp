@@ -161,6 +161,11 @@ inline int var_block_len_default(int N) {
 // index streams
 void launch_boot_rows(hipStream_t s, uint64_t seed, uint32_t tag_k0, int nb, int n, int32_t *rows);
 void launch_var_boot_rows(hipStream_t s, uint64_t seed, int nb, int N, int L, int32_t *rows);
+// Distinct rows of each sample (ascending) with their multiplicities: rows
+// [nb][m] drawn from nsrc source rows -> out_rows/out_w [nb][nsrc] (first
+// ndist[k] entries valid); cnt is [nb][nsrc] scratch.
+void launch_distinct_rows(hipStream_t s, int nb, int nsrc, int m, const int32_t *rows, int32_t *cnt,
+                          int32_t *out_rows, int32_t *out_w, int32_t *ndist);
 void launch_split(hipStream_t s, uint64_t seed, uint32_t tag, int nb, int cnt, int ntrain,
                   uint8_t *is_train);
 void launch_compact_rows(hipStream_t s, int nb, int cnt, const uint8_t *is_train, int ntrain,
@@ -174,6 +179,13 @@ void launch_expand_blocks(hipStream_t s, int nb, int nblk, int N, int L, const u
 void launch_gram_f64(hipStream_t s, int nb, int m, const int32_t *rows, const int32_t *mcount,
                      int p, const double *X, int ldx, int pe, const double *Y, int ldy,
                      double *G, double *C, double *ss = nullptr, int role = 0);
+// Weighted form over distinct rows: G[b] = sum_r w[b][r] x_r x_r' / div (likewise
+// C, ss), rows and weights at stride m, mcount[b] of them.  With w the draw
+// multiplicities and div the number of draws this equals the Gram of the sample
+// with repeated rows.
+void launch_gram_f64_weighted(hipStream_t s, int nb, int m, const int32_t *rows, const int32_t *w,
+                              const int32_t *mcount, int div, int p, const double *X, int ldx, int pe,
+                              const double *Y, int ldy, double *G, double *C, double *ss = nullptr);
 // G[b][j][i] = G[b][i][j] for i > j (upper triangle from the lower one)
 void launch_symmetrize(hipStream_t s, int nb, int p, double *G);
 // sum of squares of Y columns over sampled rows / m:  ss[b*pe + e]

@@ -39,6 +39,8 @@ struct GramArgs {
     int ldy;
     double *G, *C, *ss;  // ss: mean squares of the augmented responses (nullable)
     int T, Tc;
+    const int32_t *wt;   // per-row weights (multiplicities) at stride m, or null
+    int div;             // divisor of the sums (0: the row count)
 };
 
 // value of augmented column j of sampled row r
@@ -91,6 +93,7 @@ __global__ __launch_bounds__(256, 2) void k_gram_f64(GramArgs g) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[a][c] = dx4{0, 0, 0, 0};
 
+    const int32_t *wb = g.wt ? g.wt + (size_t)b * g.m : nullptr;
     int idx1[8], idx2[8];
     double ra[8], rbv[8];
     auto load_idx = [&](int k0, int (&idx)[8]) {
@@ -100,6 +103,8 @@ __global__ __launch_bounds__(256, 2) void k_gram_f64(GramArgs g) {
             idx[q] = k < mb ? rb[k] : -1;
         }
     };
+    // weights are read with the values (same position, already known)
+    int kpos = 0;
     auto load_val = [&](const int (&idx)[8]) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
@@ -107,6 +112,7 @@ __global__ __launch_bounds__(256, 2) void k_gram_f64(GramArgs g) {
             if (idx[q] >= 0) {
                 size_t r = (size_t)idx[q];
                 va = ia < naug ? aug_col(g, r, ia) : 0.0;
+                if (wb) va *= (double)wb[kpos + kk0 + 2 * q];
                 if (isC) vb = jb < g.pe ? g.Y[r * g.ldy + jb] : 0.0;
                 else vb = jb < naug ? aug_col(g, r, jb) : 0.0;
             }
@@ -126,6 +132,7 @@ __global__ __launch_bounds__(256, 2) void k_gram_f64(GramArgs g) {
     load_idx(0, idx1);
     load_val(idx1);
     load_idx(GK, idx1);
+    kpos = GK;
     store();
     __syncthreads();
     for (int c = 0; c < nchunk; ++c) {
@@ -133,6 +140,7 @@ __global__ __launch_bounds__(256, 2) void k_gram_f64(GramArgs g) {
         if (more) {
             load_val(idx1);                      // values of chunk c+1
             load_idx((c + 2) * GK, idx2);        // indices of chunk c+2
+            kpos += GK;
         }
 #pragma unroll
         for (int s = 0; s < GK / 4; ++s) {
@@ -155,7 +163,7 @@ __global__ __launch_bounds__(256, 2) void k_gram_f64(GramArgs g) {
         __syncthreads();
     }
 
-    const double inv = 1.0 / (double)mb;
+    const double inv = 1.0 / (double)(g.div > 0 ? g.div : mb);
     const size_t gb = (size_t)b * g.p;
 #pragma unroll
     for (int fm = 0; fm < 4; ++fm)
@@ -241,6 +249,22 @@ void launch_gram_f64(hipStream_t s, int nb, int m, const int32_t *rows, const in
         hipLaunchKernelGGL(k_gram_f64<0>, dim3(tiles, nb), dim3(256), 0, s, g);
     else
         hipLaunchKernelGGL(k_gram_f64<1>, dim3(tiles, nb), dim3(256), 0, s, g);
+    UOI_LAUNCH_CHECK();
+}
+
+void launch_gram_f64_weighted(hipStream_t s, int nb, int m, const int32_t *rows, const int32_t *w,
+                              const int32_t *mcount, int div, int p, const double *X, int ldx, int pe,
+                              const double *Y, int ldy, double *G, double *C, double *ss) {
+    GramArgs g{};
+    g.m = m; g.rows = rows; g.mcount = mcount; g.p = p; g.X = X; g.ldx = ldx;
+    g.Y = Y; g.ldy = ldy; g.G = G; g.C = C; g.ss = ss; g.wt = w; g.div = div;
+    const bool aug = C != nullptr && pe > 0 && pe < AUG_MAX;
+    g.pa = aug ? pe : 0;
+    g.pe = (C != nullptr && !aug) ? pe : 0;
+    g.T = (int)cdiv(p + g.pa, GT);
+    g.Tc = g.pe > 0 ? (int)cdiv(g.pe, GT) : 0;
+    const int tiles = g.T * (g.T + 1) / 2 + (int)cdiv(p, GT) * g.Tc;
+    hipLaunchKernelGGL(k_gram_f64<0>, dim3(tiles, nb), dim3(256), 0, s, g);
     UOI_LAUNCH_CHECK();
 }
 

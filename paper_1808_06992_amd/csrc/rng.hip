@@ -135,6 +135,54 @@ __global__ __launch_bounds__(256) void k_expand_blocks(int nblk, int N, int L,
     }
 }
 
+// Multiplicities of the source rows in a sample: cnt[k][r] = number of draws of
+// row r (cnt zeroed by the caller).
+__global__ void k_count_rows(int nsrc, int m, const int32_t *__restrict__ rows, int32_t *__restrict__ cnt) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int k = blockIdx.y;
+    if (i < m) atomicAdd(&cnt[(size_t)k * nsrc + rows[(size_t)k * m + i]], 1);
+}
+
+// Distinct rows of each sample in ascending order with their multiplicities
+// (one block per sample): out_rows[k][0..nd), out_w[k][0..nd), nd = ndist[k].
+__global__ __launch_bounds__(256) void k_distinct_rows(int nsrc, const int32_t *__restrict__ cnt,
+                                                       int32_t *__restrict__ out_rows,
+                                                       int32_t *__restrict__ out_w,
+                                                       int32_t *__restrict__ ndist) {
+    __shared__ int wtot[4];
+    __shared__ int base_s;
+    const int k = blockIdx.x;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int32_t *c = cnt + (size_t)k * nsrc;
+    int32_t *orow = out_rows + (size_t)k * nsrc;
+    int32_t *ow = out_w + (size_t)k * nsrc;
+    if (threadIdx.x == 0) base_s = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 < nsrc; c0 += 256) {
+        const int i = c0 + threadIdx.x;
+        const int ci = i < nsrc ? c[i] : 0;
+        const bool t = ci > 0;
+        const unsigned long long bal = __ballot(t);
+        const int pre = __popcll(bal & ((1ull << lane) - 1ull));
+        if (lane == 0) wtot[wid] = __popcll(bal);
+        __syncthreads();
+        int woff = 0, tot = 0;
+        for (int w = 0; w < 4; ++w) {
+            if (w < wid) woff += wtot[w];
+            tot += wtot[w];
+        }
+        const int base = base_s;
+        if (t) {
+            orow[base + woff + pre] = i;
+            ow[base + woff + pre] = ci;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) base_s = base + tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) ndist[k] = base_s;
+}
+
 __global__ void k_finite(const double *__restrict__ x, size_t n, int *flag) {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -145,6 +193,14 @@ __global__ void k_finite(const double *__restrict__ x, size_t n, int *flag) {
 
 void launch_boot_rows(hipStream_t s, uint64_t seed, uint32_t, int nb, int n, int32_t *rows) {
     hipLaunchKernelGGL(k_boot_rows, dim3(cdiv(n, 256), nb), dim3(256), 0, s, seed, n, rows);
+    UOI_LAUNCH_CHECK();
+}
+
+void launch_distinct_rows(hipStream_t s, int nb, int nsrc, int m, const int32_t *rows, int32_t *cnt,
+                          int32_t *out_rows, int32_t *out_w, int32_t *ndist) {
+    UOI_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (size_t)nb * nsrc, s));
+    hipLaunchKernelGGL(k_count_rows, dim3(cdiv(m, 256), nb), dim3(256), 0, s, nsrc, m, rows, cnt);
+    hipLaunchKernelGGL(k_distinct_rows, dim3(nb), dim3(256), 0, s, nsrc, cnt, out_rows, out_w, ndist);
     UOI_LAUNCH_CHECK();
 }
 
