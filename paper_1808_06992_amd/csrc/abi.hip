@@ -556,8 +556,9 @@ int uoi_gram(int32_t nb, int32_t m, const int32_t *rows, int32_t p, const double
         UOI_REQUIRE(nb >= 1 && m >= 1 && p >= 1 && pe >= 0 && ldx >= p, "invalid Gram sizes");
         UOI_REQUIRE(rows && X && G, "NULL pointer");
         UOI_REQUIRE(pe == 0 || (Y && C && ldy >= pe), "pe > 0 needs Y, C and ldy >= pe");
+        // the instance for products other than the fits' selection Grams
         launch_gram_f64((hipStream_t)stream, nb, m, rows, nullptr, p, X, ldx, pe, Y, ldy, G,
-                        pe ? C : nullptr);
+                        pe ? C : nullptr, nullptr, 1);
         UOI_HIP(hipStreamSynchronize((hipStream_t)stream));
         return UOI_OK;
     });
