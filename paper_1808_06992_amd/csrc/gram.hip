@@ -52,7 +52,7 @@ __device__ __forceinline__ double aug_col(const GramArgs &g, size_t r, int j) {
 
 // ROLE only names the instance (0: selection products of the bootstrap samples,
 // 1: estimation products), so kernel profiles keep the two apart.
-template <int ROLE>
+template <int ROLE, bool WGT>
 __global__ __launch_bounds__(256, 2) void k_gram_f64(GramArgs g) {
     __shared__ double As[GK][GT];
     __shared__ double Bs[GK][GT];
@@ -93,54 +93,65 @@ __global__ __launch_bounds__(256, 2) void k_gram_f64(GramArgs g) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[a][c] = dx4{0, 0, 0, 0};
 
-    const int32_t *wb = g.wt ? g.wt + (size_t)b * g.m : nullptr;
-    int idx1[8], idx2[8];
+    // Column sources of this thread's staged values are fixed for the kernel: a
+    // valid base pointer and stride per side, and a 0/1 factor for columns past
+    // the augmented width.  Loads are then issued without branches (rows past the
+    // sample read row 0 and are zeroed), so a chunk's loads are all in flight
+    // together instead of one at a time.
+    const double *pa = g.X, *pb = g.X;
+    int lda = g.ldx, ldb = g.ldx;
+    double am = 0.0, bm = 0.0;
+    if (ia < g.p) { pa = g.X + ia; am = 1.0; }
+    else if (ia < naug) { pa = g.Y + (ia - g.p); lda = g.ldy; am = 1.0; }
+    if (isC) {
+        if (jb < g.pe) { pb = g.Y + jb; ldb = g.ldy; bm = 1.0; }
+    } else if (jb < g.p) { pb = g.X + jb; bm = 1.0; }
+    else if (jb < naug) { pb = g.Y + (jb - g.p); ldb = g.ldy; bm = 1.0; }
+    const int32_t *wb = WGT ? g.wt + (size_t)b * g.m : nullptr;
+    // Row indices and weights of a chunk are requested two chunks ahead and kept
+    // as loaded (the validity test and the conversion happen at their use), so no
+    // wait is needed until then.
+    int idx1[8], idx2[8], wi1[8], wi2[8];
     double ra[8], rbv[8];
-    auto load_idx = [&](int k0, int (&idx)[8]) {
+    auto load_idx = [&](int k0, int (&idx)[8], int (&wi)[8]) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            int k = k0 + kk0 + 2 * q;
-            idx[q] = k < mb ? rb[k] : -1;
+            const int k = k0 + kk0 + 2 * q;
+            const int kc = k < mb ? k : 0;
+            idx[q] = rb[kc];
+            if (WGT) wi[q] = wb[kc];
         }
     };
-    // weights are read with the values (same position, already known)
-    int kpos = 0;
-    auto load_val = [&](const int (&idx)[8]) {
+    // values of the chunk starting at row k0 (rows past the sample are zeroed)
+    auto load_val = [&](int k0, const int (&idx)[8]) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            double va = 0.0, vb = 0.0;
-            if (idx[q] >= 0) {
-                size_t r = (size_t)idx[q];
-                va = ia < naug ? aug_col(g, r, ia) : 0.0;
-                if (wb) va *= (double)wb[kpos + kk0 + 2 * q];
-                if (isC) vb = jb < g.pe ? g.Y[r * g.ldy + jb] : 0.0;
-                else vb = jb < naug ? aug_col(g, r, jb) : 0.0;
-            }
-            ra[q] = va;
-            rbv[q] = vb;
+            const bool ok = k0 + kk0 + 2 * q < mb;
+            const size_t r = (size_t)idx[q];
+            ra[q] = pa[r * lda] * (ok ? am : 0.0);
+            rbv[q] = pb[r * ldb] * (ok ? bm : 0.0);
         }
     };
-    auto store = [&]() {
+    auto store = [&](const int (&wi)[8]) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            As[kk0 + 2 * q][cc] = ra[q];
+            // the weight (multiplicity) on one side
+            As[kk0 + 2 * q][cc] = WGT ? ra[q] * (double)wi[q] : ra[q];
             Bs[kk0 + 2 * q][cc] = rbv[q];
         }
     };
 
     const int nchunk = (mb + GK - 1) / GK;
-    load_idx(0, idx1);
-    load_val(idx1);
-    load_idx(GK, idx1);
-    kpos = GK;
-    store();
+    load_idx(0, idx1, wi1);
+    load_val(0, idx1);
+    store(wi1);
+    load_idx(GK, idx1, wi1);
     __syncthreads();
     for (int c = 0; c < nchunk; ++c) {
         const bool more = c + 1 < nchunk;
         if (more) {
-            load_val(idx1);                      // values of chunk c+1
-            load_idx((c + 2) * GK, idx2);        // indices of chunk c+2
-            kpos += GK;
+            load_val((c + 1) * GK, idx1);        // values of chunk c+1
+            load_idx((c + 2) * GK, idx2, wi2);   // indices and weights of chunk c+2
         }
 #pragma unroll
         for (int s = 0; s < GK / 4; ++s) {
@@ -156,9 +167,12 @@ __global__ __launch_bounds__(256, 2) void k_gram_f64(GramArgs g) {
         }
         __syncthreads();
         if (more) {
-            store();
+            store(wi1);
 #pragma unroll
-            for (int q = 0; q < 8; ++q) idx1[q] = idx2[q];
+            for (int q = 0; q < 8; ++q) {
+                idx1[q] = idx2[q];
+                wi1[q] = wi2[q];
+            }
         }
         __syncthreads();
     }
@@ -246,9 +260,9 @@ void launch_gram_f64(hipStream_t s, int nb, int m, const int32_t *rows, const in
     g.Tc = g.pe > 0 ? (int)cdiv(g.pe, GT) : 0;
     const int tiles = g.T * (g.T + 1) / 2 + (int)cdiv(p, GT) * g.Tc;
     if (role == 0)
-        hipLaunchKernelGGL(k_gram_f64<0>, dim3(tiles, nb), dim3(256), 0, s, g);
+        hipLaunchKernelGGL((k_gram_f64<0, false>), dim3(tiles, nb), dim3(256), 0, s, g);
     else
-        hipLaunchKernelGGL(k_gram_f64<1>, dim3(tiles, nb), dim3(256), 0, s, g);
+        hipLaunchKernelGGL((k_gram_f64<1, false>), dim3(tiles, nb), dim3(256), 0, s, g);
     UOI_LAUNCH_CHECK();
 }
 
@@ -264,7 +278,7 @@ void launch_gram_f64_weighted(hipStream_t s, int nb, int m, const int32_t *rows,
     g.T = (int)cdiv(p + g.pa, GT);
     g.Tc = g.pe > 0 ? (int)cdiv(g.pe, GT) : 0;
     const int tiles = g.T * (g.T + 1) / 2 + (int)cdiv(p, GT) * g.Tc;
-    hipLaunchKernelGGL(k_gram_f64<0>, dim3(tiles, nb), dim3(256), 0, s, g);
+    hipLaunchKernelGGL((k_gram_f64<0, true>), dim3(tiles, nb), dim3(256), 0, s, g);
     UOI_LAUNCH_CHECK();
 }
 
