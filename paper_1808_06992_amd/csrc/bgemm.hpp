@@ -66,41 +66,46 @@ __global__ __launch_bounds__(256) void k_bgemm(int p, int R, const T *__restrict
         iok[a] = icol[a] < p;
     }
 
+    // All loads are issued unconditionally from clamped (valid, finite) addresses
+    // and masked only where the values are used, so that the loads of a chunk stay
+    // in flight together: rows of V past p are zeroed when staged (which also
+    // cancels the clamped A rows past p), columns past R and rows of A past p only
+    // reach outputs that the epilogue discards.
     // V chunk loader: KC*TN values over 256 threads
     constexpr int VPT = (BG_KC * TN + 255) / 256;
     T vreg[VPT];
     auto load_v = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < VPT; ++q) {
-            int e = tid + 256 * q;
-            int kk = e / TN, cc = e % TN;
-            T v = T(0);
-            if (e < BG_KC * TN && k0 + kk < p && r0 + cc < R) v = Vb[(size_t)(k0 + kk) * R + r0 + cc];
-            vreg[q] = v;
+            const int e = min(tid + 256 * q, BG_KC * TN - 1);
+            const int kk = min(k0 + e / TN, p - 1), cc = min(r0 + e % TN, R - 1);
+            vreg[q] = Vb[(size_t)kk * R + cc];
         }
     };
-    auto store_v = [&](int buf) {
+    auto store_v = [&](int buf, int k0) {
 #pragma unroll
         for (int q = 0; q < VPT; ++q) {
-            int e = tid + 256 * q;
-            if (e < BG_KC * TN) Vs[buf][e / TN][e % TN] = vreg[q];
+            const int e = tid + 256 * q;
+            if (e < BG_KC * TN) Vs[buf][e / TN][e % TN] = k0 + e / TN < p ? vreg[q] : T(0);
         }
     };
+    int icl[FM];
+#pragma unroll
+    for (int a = 0; a < FM; ++a) icl[a] = min(icol[a], p - 1);
     T areg[BG_KC / 4][FM];
     auto load_a = [&](int k0) {
 #pragma unroll
         for (int s = 0; s < BG_KC / 4; ++s) {
-            const int k = k0 + 4 * s + lk;
+            const int k = min(k0 + 4 * s + lk, p - 1);
 #pragma unroll
-            for (int a = 0; a < FM; ++a)
-                areg[s][a] = (iok[a] && k < p) ? Ab[(size_t)k * p + icol[a]] : T(0);
+            for (int a = 0; a < FM; ++a) areg[s][a] = Ab[(size_t)k * p + icl[a]];
         }
     };
 
     const int nchunk = (p + BG_KC - 1) / BG_KC;
     load_v(0);
     load_a(0);
-    store_v(0);
+    store_v(0, 0);
     __syncthreads();
     for (int c = 0; c < nchunk; ++c) {
         const int cur = c & 1;
@@ -123,7 +128,7 @@ __global__ __launch_bounds__(256) void k_bgemm(int p, int R, const T *__restrict
                     const T bv = Vs[cur][4 * s + lk][16 * cc + lr];
                     acc[a][cc] = mfma16x16x4(acur[s][a], bv, acc[a][cc]);
                 }
-        if (more) store_v(cur ^ 1);
+        if (more) store_v(cur ^ 1, (c + 1) * BG_KC);
         __syncthreads();
     }
     if (i_base < p) epi.apply(b, i_base, r0, lr, lk, acc);
