@@ -156,18 +156,37 @@ __global__ __launch_bounds__(256) void k_panel(int p, int k0, int kb, const doub
     double *Wb = Wt + (size_t)b * p * NB;
     double *Ob = Ot + (size_t)b * p * NB;
     const bool above = i0 < k0;
-    for (int e = threadIdx.x; e < 64 * NB; e += 256) {
+    // all loads of the panel first (clamped, unconditional), then the stores
+    constexpr int PER = 64 * NB / 256;
+    double pv[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = threadIdx.x + 256 * q;
         int r, t;
         if (above) { t = e / 64; r = e % 64; }   // coalesced along i
         else { r = e / NB; t = e % NB; }          // coalesced along k
-        double v = 0.0;
-        if (i0 + r < p && t < kb) {
-            v = above ? Ab[(size_t)(k0 + t) * p + i0 + r] : Ab[(size_t)(i0 + r) * p + k0 + t];
-            if (i0 + r == k0 + t) v += shift;
-        }
-        As[t * LD + r] = v;
+        const int gi = min(i0 + r, p - 1), gk = min(k0 + t, p - 1);
+        pv[q] = above ? Ab[(size_t)gk * p + gi] : Ab[(size_t)gi * p + gk];
     }
-    for (int e = threadIdx.x; e < NB * NB; e += 256) Qs[(e / NB) * LD + e % NB] = Qb[e];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = threadIdx.x + 256 * q;
+        int r, t;
+        if (above) { t = e / 64; r = e % 64; }
+        else { r = e / NB; t = e % NB; }
+        const bool ok = i0 + r < p && t < kb;
+        As[t * LD + r] = ok ? pv[q] + (i0 + r == k0 + t ? shift : 0.0) : 0.0;
+    }
+    {
+        double qv[NB * NB / 256];
+#pragma unroll
+        for (int q = 0; q < NB * NB / 256; ++q) qv[q] = Qb[threadIdx.x + 256 * q];
+#pragma unroll
+        for (int q = 0; q < NB * NB / 256; ++q) {
+            const int e = threadIdx.x + 256 * q;
+            Qs[(e / NB) * LD + e % NB] = qv[q];
+        }
+    }
     __syncthreads();
     for (int e = threadIdx.x; e < 64 * NB; e += 256) {
         const int t = e / 64, r = e % 64;
@@ -234,12 +253,16 @@ __global__ __launch_bounds__(256) void k_update(int p, int k0, int kb, const dou
         for (int fn = 0; fn < 2; ++fn)
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                const int i = ib + fm * 16 + mfma_row(0.0, lk, t), j = jb + fn * 16 + lr;
-                old[fm][fn][t] = (i < p && j < p) ? Ab[(size_t)i * p + j] + (i == j ? shift : 0.0) : 0.0;
+                // clamped (valid) addresses: values outside the matrix are never stored
+                const int i = min(ib + fm * 16 + mfma_row(0.0, lk, t), p - 1);
+                const int j = min(jb + fn * 16 + lr, p - 1);
+                old[fm][fn][t] = Ab[(size_t)i * p + j] + (i == j ? shift : 0.0);
             }
     const double *Wb = Wt + (size_t)b * p * NB;
     const double *Ob = Ot + (size_t)b * p * NB;
-    const int ia0 = ib + lr, ia1 = ib + 16 + lr, jb0 = jb + lr, jb1 = jb + 16 + lr;
+    // operand rows past p only reach outputs that are not stored: read clamped
+    const int ia0 = min(ib + lr, p - 1), ia1 = min(ib + 16 + lr, p - 1);
+    const int jb0 = min(jb + lr, p - 1), jb1 = min(jb + 16 + lr, p - 1);
     dx4 acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -249,8 +272,8 @@ __global__ __launch_bounds__(256) void k_update(int p, int k0, int kb, const dou
     for (int s = 0; s < NB / 4; ++s) {
         const int t = 4 * s + lk;  // rows t >= kb of the panels are zero
         const size_t o = (size_t)t * p;
-        const double a0 = ia0 < p ? Wb[o + ia0] : 0.0, a1 = ia1 < p ? Wb[o + ia1] : 0.0;
-        const double b0 = jb0 < p ? Ob[o + jb0] : 0.0, b1 = jb1 < p ? Ob[o + jb1] : 0.0;
+        const double a0 = Wb[o + ia0], a1 = Wb[o + ia1];
+        const double b0 = Ob[o + jb0], b1 = Ob[o + jb1];
         acc[0][0] = mfma16x16x4(a0, b0, acc[0][0]);
         acc[0][1] = mfma16x16x4(a0, b1, acc[0][1]);
         acc[1][0] = mfma16x16x4(a1, b0, acc[1][0]);
