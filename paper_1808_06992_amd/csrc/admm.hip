@@ -56,44 +56,45 @@ struct AdmmEpi {
     int p, R, pe;
     T rho, inv_rho, alpha;  // alpha: over-relaxation (1 = none)
     __device__ bool tile_active(int b, int r0, int w) const {
-        int hi = min(R, r0 + w);
-        for (int r = r0; r < hi; ++r)
-            if (state[(size_t)b * R + r] == 0) return true;
-        return false;
+        // one state byte per lane (w <= 64), combined by a ballot: the same answer
+        // in every wave of the workgroup
+        const int lane = threadIdx.x & 63, r = r0 + lane;
+        const bool a = lane < w && r < R && state[(size_t)b * R + min(r, R - 1)] == 0;
+        return __ballot(a) != 0ull;
     }
     template <class Acc>
     __device__ void apply(int b, int i_base, int r0, int lr, int lk, Acc (&acc)[FM][FN]) const {
-        // all loads of the tile first (the stores below may not be reordered above
-        // them by the compiler), then the threshold / dual update and the stores
-        T hv[FM][4], uv[FN][FM][4], zv[FN][FM][4];
+        // All loads of the tile first, unconditionally from clamped (valid)
+        // addresses, so that they are in flight together; the state masks only the
+        // stores.  Then the threshold / dual update and the stores.
+        T hv[FN][FM][4], uv[FN][FM][4], zv[FN][FM][4], thr[FN];
         const bool relaxed = alpha != T(1);
         bool act[FN];
+        int rc[FN];
 #pragma unroll
         for (int c = 0; c < FN; ++c) {
             const int r = r0 + 16 * c + lr;
-            act[c] = r < R && state[(size_t)b * R + r] == 0;
+            rc[c] = min(r, R - 1);
+            act[c] = r < R && state[(size_t)b * R + rc[c]] == 0;
+            thr[c] = (T)lam[rc[c] / pe] * inv_rho;
         }
 #pragma unroll
         for (int a = 0; a < FM; ++a)
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                const int i = i_base + 16 * a + mfma_row(T(0), lk, t);
+                const int ic = min(i_base + 16 * a + mfma_row(T(0), lk, t), p - 1);
 #pragma unroll
                 for (int c = 0; c < FN; ++c) {
-                    const int r = r0 + 16 * c + lr;
-                    const bool ok = act[c] && i < p;
-                    uv[c][a][t] = ok ? u[((size_t)b * p + i) * R + r] : T(0);
-                    zv[c][a][t] = (ok && relaxed) ? z[((size_t)b * p + i) * R + r] : T(0);
-                    if (c == 0) hv[a][t] = T(0);
-                    if (ok && pe == 1) hv[a][t] = h[(size_t)b * p + i];
+                    const size_t o = ((size_t)b * p + ic) * R + rc[c];
+                    uv[c][a][t] = u[o];
+                    zv[c][a][t] = relaxed ? z[o] : T(0);
+                    hv[c][a][t] = h[((size_t)b * p + ic) * pe + rc[c] % pe];
                 }
             }
 #pragma unroll
         for (int c = 0; c < FN; ++c) {
-            const int r = r0 + 16 * c + lr;
             if (!act[c]) continue;
-            const int e = r % pe;
-            const T thr = (T)lam[r / pe] * inv_rho;
+            const int r = r0 + 16 * c + lr;
 #pragma unroll
             for (int a = 0; a < FM; ++a)
 #pragma unroll
@@ -101,11 +102,10 @@ struct AdmmEpi {
                     const int i = i_base + 16 * a + mfma_row(T(0), lk, t);
                     if (i >= p) continue;
                     const size_t o = ((size_t)b * p + i) * R + r;
-                    const T hh = pe == 1 ? hv[a][t] : h[((size_t)b * p + i) * pe + e];
-                    T x = hh + rho * (T)acc[a][c][t];
+                    T x = hv[c][a][t] + rho * (T)acc[a][c][t];
                     if (relaxed) x = alpha * x + (T(1) - alpha) * zv[c][a][t];
                     const T uo = uv[c][a][t];
-                    const T zn = soft_threshold(x + uo, thr);
+                    const T zn = soft_threshold(x + uo, thr[c]);
                     const T un = uo + x - zn;
                     z[o] = zn;
                     u[o] = un;
@@ -129,35 +129,49 @@ struct KktEpi {
     bool only_active;
     __device__ bool tile_active(int b, int r0, int w) const {
         if (!only_active) return true;
-        int hi = min(R, r0 + w);
-        for (int r = r0; r < hi; ++r)
-            if (state[(size_t)b * R + r] == 0) return true;
-        return false;
+        const int lane = threadIdx.x & 63, r = r0 + lane;
+        const bool a = lane < w && r < R && state[(size_t)b * R + min(r, R - 1)] == 0;
+        return __ballot(a) != 0ull;
     }
     template <class Acc>
     __device__ void apply(int b, int i_base, int r0, int lr, int lk, Acc (&acc)[FM][FN]) const {
+        // loads first, unconditionally from clamped addresses (see AdmmEpi)
+        double cv[FN][FM][4], zv[FN][FM][4], lm[FN];
+        bool rok[FN];
 #pragma unroll
         for (int c = 0; c < FN; ++c) {
-            int r = r0 + 16 * c + lr;
-            bool rok = r < R && !(only_active && state[(size_t)b * R + r] != 0);
-            int e = rok ? r % pe : 0;
-            double lm = rok ? lam[r / pe] : 0.0;
+            const int r = r0 + 16 * c + lr;
+            const int rc = min(r, R - 1);
+            rok[c] = r < R && !(only_active && state[(size_t)b * R + rc] != 0);
+            lm[c] = lam[rc / pe];
+#pragma unroll
+            for (int a = 0; a < FM; ++a)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int ic = min(i_base + 16 * a + mfma_row(T(0), lk, t), p - 1);
+                    cv[c][a][t] = C[((size_t)b * p + ic) * pe + rc % pe];
+                    zv[c][a][t] = (double)z[((size_t)b * p + ic) * R + rc];
+                }
+        }
+#pragma unroll
+        for (int c = 0; c < FN; ++c) {
+            const int r = r0 + 16 * c + lr;
             double m = 0.0;
 #pragma unroll
             for (int a = 0; a < FM; ++a)
+#pragma unroll
                 for (int t = 0; t < 4; ++t) {
-                    int i = i_base + 16 * a + mfma_row(T(0), lk, t);
-                    if (!rok || i >= p) continue;
-                    size_t o = ((size_t)b * p + i) * R + r;
-                    double g = C[((size_t)b * p + i) * pe + e] - (double)acc[a][c][t];
-                    double zi = (double)z[o];
-                    double v = zi != 0.0 ? fabs(g - (zi > 0 ? lm : -lm)) : fmax(0.0, fabs(g) - lm);
+                    const int i = i_base + 16 * a + mfma_row(T(0), lk, t);
+                    if (!rok[c] || i >= p) continue;
+                    const double g = cv[c][a][t] - (double)acc[a][c][t];
+                    const double zi = zv[c][a][t];
+                    const double v = zi != 0.0 ? fabs(g - (zi > 0 ? lm[c] : -lm[c])) : fmax(0.0, fabs(g) - lm[c]);
                     m = fmax(m, v);
                 }
             // lanes lr, lr+16, lr+32, lr+48 hold the same solve
             m = fmax(m, __shfl_xor(m, 16));
             m = fmax(m, __shfl_xor(m, 32));
-            if (rok && lk == 0 && m > 0.0) atomic_max_nonneg(&vmax[(size_t)b * R + r], m);
+            if (rok[c] && lk == 0 && m > 0.0) atomic_max_nonneg(&vmax[(size_t)b * R + r], m);
         }
     }
 };

@@ -304,25 +304,26 @@ struct CgEpi {
     double *AP, *pAp;
     int p, nL, W;
     __device__ bool tile_active(int b, int r0, int w) const {
-        int hi = min(nL, r0 + w);
-        for (int r = r0; r < hi; ++r)
-            if (state[(size_t)b * nL + r] == 0) return true;
-        return false;
+        const int lane = threadIdx.x & 63, r = r0 + lane;
+        const bool a = lane < w && r < nL && state[(size_t)b * nL + min(r, nL - 1)] == 0;
+        return __ballot(a) != 0ull;
     }
     template <class Acc, int FM, int FN>
     __device__ void apply_impl(int b, int i_base, int r0, int lr, int lk, Acc (&acc)[FM][FN]) const {
         for (int c = 0; c < FN; ++c) {
             int r = r0 + 16 * c + lr;
-            bool ok = r < nL && state[(size_t)b * nL + r] == 0;
-            const uint64_t *sw = ok ? supp + (size_t)Lidx[r] * W : nullptr;
+            const int rc = min(r, nL - 1);
+            bool ok = r < nL && state[(size_t)b * nL + rc] == 0;
+            const uint64_t *sw = supp + (size_t)Lidx[rc] * W;
             double pv[FM][4];
             bool mk[FM][4];
-            for (int a = 0; a < FM; ++a)  // loads before the stores of AP
+            for (int a = 0; a < FM; ++a)  // loads before the stores of AP, from clamped addresses
                 for (int t = 0; t < 4; ++t) {
                     int i = i_base + 16 * a + mfma_row(0.0, lk, t);
+                    const int ic = min(i, p - 1);
                     bool in = ok && i < p;
-                    mk[a][t] = in && ((sw[i >> 6] >> (i & 63)) & 1ull);
-                    pv[a][t] = in ? P[((size_t)b * p + i) * nL + r] : 0.0;
+                    mk[a][t] = in && ((sw[ic >> 6] >> (ic & 63)) & 1ull);
+                    pv[a][t] = in ? P[((size_t)b * p + ic) * nL + rc] : 0.0;
                 }
             double part = 0.0;
             for (int a = 0; a < FM; ++a)
