@@ -54,7 +54,7 @@ KERNELS = {
     "admm32": ("uoi::k_bgemm<float, 1, N, uoi::AdmmEpi<float, 1, N> >", ["bgemm.hpp", "admm.hip", "common.hpp"]),
     "admm64": ("uoi::k_bgemm<double, 1, N, uoi::AdmmEpi<double, 1, N> >", ["bgemm.hpp", "admm.hip", "common.hpp"]),
     "plain": ("uoi::k_admm_plain", ["admm.hip", "common.hpp"]),
-    "gram": ("uoi::k_gram_f64<0>", ["gram.hip", "common.hpp"]),
+    "gram": ("uoi::k_gram_f64<0, true>", ["gram.hip", "common.hpp"]),
 }
 
 
