@@ -111,9 +111,16 @@ __global__ __launch_bounds__(256) void k_ols_small(int p, int pe, int R, int W,
     const double *CTb = CT + (size_t)k * p * pe;
     const int s = support_members(supp + (size_t)r * W, W, idx);
     if (threadIdx.x == 0) fail = 0;
-    for (int t = threadIdx.x; t < s * s; t += 256) {
-        int a = t / s, c = t % s;
-        Ls[t] = GTb[(size_t)idx[a] * p + idx[c]];
+    for (int t0 = threadIdx.x; t0 < s * s; t0 += 1024) {  // four gathers in flight
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int t = min(t0 + 256 * u, s * s - 1);
+            v[u] = GTb[(size_t)idx[t / s] * p + idx[t % s]];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (t0 + 256 * u < s * s) Ls[t0 + 256 * u] = v[u];
     }
     for (int a = threadIdx.x; a < s; a += 256) bv[a] = CTb[(size_t)idx[a] * pe + e];
     __syncthreads();
@@ -194,14 +201,24 @@ __global__ __launch_bounds__(256) void k_ols_mid(int p, int pe, int R, int W,
     for (int kb = 0; kb < s; kb += kPW) {
         const int nbk = min(kPW, s - kb);
         const int m = s + 1 - kb;  // panel rows kb..s (row s is the right-hand side)
-        for (int q = tid; q < m * kPW; q += 256) {
-            const int c = q / m, i = q % m;
-            double v = 0.0;
-            if (c < nbk) {
+        {   // all loads of the panel first (clamped, unconditional), then the stores
+            constexpr int MAXQ = ((kMid + 1) * kPW + 255) / 256;
+            double pv[MAXQ];
+#pragma unroll
+            for (int u = 0; u < MAXQ; ++u) {
+                const int q = tid + 256 * u;
+                const int c = min(q / m, nbk - 1), i = min(q % m, m - 1);
                 const int gi = kb + i, gc = idx[kb + c];
-                v = gi < s ? GTb[(size_t)gc * p + idx[gi]] : CTb[(size_t)gc * pe + e];
+                pv[u] = gi < s ? GTb[(size_t)gc * p + idx[gi]] : CTb[(size_t)gc * pe + e];
             }
-            Pn[i * LDP + c] = v;
+#pragma unroll
+            for (int u = 0; u < MAXQ; ++u) {
+                const int q = tid + 256 * u;
+                if (q < m * kPW) {
+                    const int c = q / m, i = q % m;
+                    Pn[i * LDP + c] = c < nbk ? pv[u] : 0.0;
+                }
+            }
         }
         __syncthreads();
         // left-looking: subtract the contribution of the factored columns 0..kb
@@ -216,10 +233,16 @@ __global__ __launch_bounds__(256) void k_ols_mid(int p, int pe, int R, int W,
                 double acc[kPW];
 #pragma unroll
                 for (int c = 0; c < kPW; ++c) acc[c] = Pn[i * LDP + c];
-                for (int t = 0; t < nt; ++t) {
-                    const double a = L[(size_t)(t0 + t) * ld + kb + i];
+                for (int t = 0; t < nt; t += 8) {
+                    // eight factor entries in flight at once; columns past nt are read
+                    // clamped (finite) and meet zero rows of Lp
+                    double a[8];
 #pragma unroll
-                    for (int c = 0; c < kPW; ++c) acc[c] -= a * Lp[t][c];
+                    for (int u = 0; u < 8; ++u) a[u] = L[(size_t)(t0 + min(t + u, nt - 1)) * ld + kb + i];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+#pragma unroll
+                        for (int c = 0; c < kPW; ++c) acc[c] -= a[u] * Lp[t + u][c];
                 }
 #pragma unroll
                 for (int c = 0; c < kPW; ++c) Pn[i * LDP + c] = acc[c];
@@ -259,7 +282,14 @@ __global__ __launch_bounds__(256) void k_ols_mid(int p, int pe, int R, int W,
             const int t = t0 + tt;
             double part = 0.0;
             if (t < t1)
-                for (int i = t1 + g; i < s; i += 8) part += L[(size_t)t * ld + i] * xv[i];
+                for (int i0 = t1 + g; i0 < s; i0 += 32) {
+                    double lv[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) lv[u] = L[(size_t)t * ld + min(i0 + 8 * u, s - 1)];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (i0 + 8 * u < s) part += lv[u] * xv[i0 + 8 * u];
+                }
             red[g][tt] = part;
         }
         __syncthreads();

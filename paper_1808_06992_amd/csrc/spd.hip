@@ -103,10 +103,14 @@ __global__ __launch_bounds__(256) void k_pivot(int p, int k0, int kb, const doub
     const double *Ab = src + (size_t)b * p * p;
     double v[16];
 #pragma unroll
+    for (int a = 0; a < 16; ++a) {  // loads from clamped addresses, all in flight together
+        const int i = ty + 4 * a;
+        v[a] = Ab[(size_t)(k0 + min(i, kb - 1)) * p + k0 + min(tx, kb - 1)];
+    }
+#pragma unroll
     for (int a = 0; a < 16; ++a) {
         const int i = ty + 4 * a;
-        v[a] = (i < kb && tx < kb) ? Ab[(size_t)(k0 + i) * p + k0 + tx] + (i == tx ? shift : 0.0)
-                                   : (i == tx ? 1.0 : 0.0);
+        v[a] = (i < kb && tx < kb) ? v[a] + (i == tx ? shift : 0.0) : (i == tx ? 1.0 : 0.0);
     }
 #pragma unroll
     for (int k = 0; k < NB; ++k) {
@@ -312,10 +316,14 @@ __global__ void k_symneg(int p, double *__restrict__ M) {
     if (bj > bi) return;
     double *Mb = M + (size_t)b * p * p;
     const int tx = threadIdx.x, ty = threadIdx.y;
-    for (int r = ty; r < 32; r += 8) {
-        const int i = bi * 32 + r, j = bj * 32 + tx;
-        if (i < p && j < p) t[r][tx] = Mb[(size_t)i * p + j];
+    double v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {  // clamped loads, all in flight together
+        const int i = min(bi * 32 + ty + 8 * q, p - 1), j = min(bj * 32 + tx, p - 1);
+        v[q] = Mb[(size_t)i * p + j];
     }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) t[ty + 8 * q][tx] = v[q];
     __syncthreads();
     for (int r = ty; r < 32; r += 8) {
         const int i = bi * 32 + r, j = bj * 32 + tx;      // lower position
