@@ -5,6 +5,7 @@
 // counts, support sizes).
 #include <cmath>
 #include <cstring>
+#include <initializer_list>
 #include <map>
 #include <mutex>
 #include <string>
@@ -27,7 +28,31 @@ struct PoolEntry {
 };
 std::mutex g_pool_mu;
 std::map<int, PoolEntry> g_pool;
+std::map<int, PoolEntry> g_pinned;
 }  // namespace
+
+int *pinned_ints(size_t n) {
+    int dev = 0;
+    UOI_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    PoolEntry &e = g_pinned[dev];
+    const size_t bytes = sizeof(int) * std::max<size_t>(n, 64);
+    if (e.cap < bytes) {
+        if (e.ptr) {
+            UOI_HIP(hipDeviceSynchronize());
+            UOI_HIP(hipHostFree(e.ptr));
+            e.ptr = nullptr;
+            e.cap = 0;
+        }
+        if (hipHostMalloc(&e.ptr, bytes) != hipSuccess) {
+            e.ptr = nullptr;
+            (void)hipGetLastError();
+            throw Error(UOI_ENOMEM, "pinned host allocation failed");
+        }
+        e.cap = bytes;
+    }
+    return (int *)e.ptr;
+}
 
 void *pool_get(size_t bytes) {
     int dev = 0;
@@ -97,21 +122,23 @@ static void check_opts(const uoi_opts *o, bool need_boot) {
     UOI_REQUIRE(o->solver == UOI_SOLVER_BATCHED || o->solver == UOI_SOLVER_PLAIN, "unknown solver");
 }
 
-static void check_finite(hipStream_t s, const double *x, size_t n, const char *what) {
-    int *flag = nullptr;
-    UOI_HIP(hipMalloc(&flag, sizeof(int)));
-    int h = 0;
-    try {
-        UOI_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
-        launch_finite_check(s, x, n, flag);
-        UOI_HIP(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s));
-        UOI_HIP(hipStreamSynchronize(s));
-    } catch (...) {
-        (void)hipFree(flag);
-        throw;
-    }
-    UOI_HIP(hipFree(flag));
-    if (h) throw Error(UOI_EINVAL, std::string(what) + " contains NaN or Inf");
+// NaN / Inf in the inputs: one flag per array in the workspace, one readback.
+struct FiniteArg {
+    const double *x;
+    size_t n;
+    const char *what;
+};
+static void check_finite(hipStream_t s, int *flags, std::initializer_list<FiniteArg> args) {
+    const int na = (int)args.size();
+    UOI_HIP(hipMemsetAsync(flags, 0, sizeof(int) * na, s));
+    int i = 0;
+    for (const FiniteArg &a : args) launch_finite_check(s, a.x, a.n, flags + i++);
+    int *h = pinned_ints(na);
+    UOI_HIP(hipMemcpyAsync(h, flags, sizeof(int) * na, hipMemcpyDeviceToHost, s));
+    UOI_HIP(hipStreamSynchronize(s));
+    i = 0;
+    for (const FiniteArg &a : args)
+        if (h[i++]) throw Error(UOI_EINVAL, std::string(a.what) + " contains NaN or Inf");
 }
 
 // z in [nb][p][R] (feature-major) <-> [nb][R][p] (solve-major)
@@ -141,7 +168,7 @@ static void transpose(hipStream_t s, int nb, int p, int R, const double *a, doub
     UOI_LAUNCH_CHECK();
 }
 
-// Host sum of n device int32 values (synchronises the stream; timing mode only).
+// Host sum of n device int32 values (after the stream has synchronised).
 static long long sum_device_ints(hipStream_t s, const int32_t *d, int n) {
     std::vector<int32_t> h(n);
     UOI_HIP(hipMemcpyAsync(h.data(), d, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
@@ -151,27 +178,24 @@ static long long sum_device_ints(hipStream_t s, const int32_t *d, int n) {
     return t;
 }
 
-// Times one launch sequence on the stream and adds it to a kernel-stat slot.
+// Times one launch sequence on the stream for a kernel-stat slot; the events are
+// read only after the fit's final synchronisation (no wait in between).
 struct KernelTimer {
     hipStream_t s;
     uoi_kstat *k;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    KernelTimer(hipStream_t s_, uoi_kstat *k_) : s(s_), k(k_) {
+    KernelTimer(hipStream_t s_, uoi_kstat *k_) : s(s_), k(k_) {}
+    void start() {
         if (!k) return;
         UOI_HIP(hipEventCreate(&e0));
         UOI_HIP(hipEventCreate(&e1));
         UOI_HIP(hipEventRecord(e0, s));
     }
-    bool stopped = false;
-    void stop() {  // end of the timed launches (done() may follow after other work)
-        if (!k || stopped) return;
-        UOI_HIP(hipEventRecord(e1, s));
-        stopped = true;
+    void stop() {
+        if (k) UOI_HIP(hipEventRecord(e1, s));
     }
-    void done(double bytes, double flops) {
+    void resolve(double bytes, double flops) {  // after the stream has synchronised
         if (!k) return;
-        stop();
-        UOI_HIP(hipEventSynchronize(e1));
         float ms = 0.f;
         UOI_HIP(hipEventElapsedTime(&ms, e0, e1));
         k->ms += ms;
@@ -219,8 +243,6 @@ static int lasso_fit(int n, int p, const double *X, const double *y, const uoi_o
     UOI_REQUIRE(ntr >= 1 && nev >= 1, "estimation split leaves an empty training or evaluation set");
     UOI_REQUIRE((int64_t)o->B1 * o->q <= (int64_t)1 << 30, "too many solves");
     hipStream_t s = (hipStream_t)o->stream;
-    check_finite(s, X, (size_t)n * p, "X");
-    check_finite(s, y, (size_t)n, "y");
     const bool timing = (o->flags & UOI_FLAG_TIMING) != 0;
     float sm[8] = {0};
     if (diag) std::memset(diag->kstat, 0, sizeof(diag->kstat));
@@ -236,7 +258,8 @@ static int lasso_fit(int n, int p, const double *X, const double *y, const uoi_o
                       double *&u, int32_t *&its, double *&kkt, uint8_t *&flag, int32_t *&tr,
                       int32_t *&ev, double *&GT, double *&CT, double *&GE, double *&CE, double *&sE,
                       void *&admm_w, void *&est_w, void *&cw) {
-        rows = a.take<int32_t>((size_t)4 * B1 * n + B1);  // draws, counts, distinct rows, weights, sizes
+        // draws, counts, distinct rows, weights, sizes, input check flags
+        rows = a.take<int32_t>((size_t)4 * B1 * n + B1 + 4);
         G = a.take<double>((size_t)B1 * p * p);
         c = a.take<double>((size_t)B1 * p);
         lam = a.take<double>(q);
@@ -265,8 +288,10 @@ static int lasso_fit(int n, int p, const double *X, const double *y, const uoi_o
     A.cap = ar.off;
     A.base = (char *)pool_get(ar.off);
     layout(A, rows, G, c, lam, z, u, its, kkt, flag, tr, ev, GT, CT, GE, CE, sE, admm_w, est_w, cw);
+    check_finite(s, rows + (size_t)4 * B1 * n + B1, {{X, (size_t)n * p, "X"}, {y, (size_t)n, "y"}});
 
     Timer tm(s, timing);
+    KernelTimer gram_timer(s, timing && diag ? &diag->kstat[UOI_KSTAT_GRAM] : nullptr);
     tm.mark();
     UOI_HIP(hipMemcpyAsync(lam, o->lambdas, sizeof(double) * q, hipMemcpyHostToDevice, s));
     // model selection: bootstrap rows, Gram, ADMM sweep, supports
@@ -277,13 +302,9 @@ static int lasso_fit(int n, int p, const double *X, const double *y, const uoi_o
         int32_t *cntb = rows + (size_t)B1 * n, *drow = cntb + (size_t)B1 * n, *dw = drow + (size_t)B1 * n;
         int32_t *nd = dw + (size_t)B1 * n;
         launch_distinct_rows(s, B1, n, n, rows, cntb, drow, dw, nd);
-        KernelTimer kt(s, timing && diag ? &diag->kstat[UOI_KSTAT_GRAM] : nullptr);
+        gram_timer.start();
         launch_gram_f64_weighted(s, B1, n, drow, dw, nd, n, p, X, p, 1, y, 1, G, c);
-        kt.stop();
-        if (timing && diag) {
-            const double md = (double)sum_device_ints(s, nd, B1);  // rows actually processed
-            kt.done(md * (p + 1) * 8 + (double)B1 * p * (p + 1) * 8, md * p * (p + 1) + 2.0 * md * p);
-        }
+        gram_timer.stop();
     }
     tm.mark();
     P.G = G;
@@ -314,6 +335,11 @@ static int lasso_fit(int n, int p, const double *X, const double *y, const uoi_o
         sm[4] = tm.between(2, 3);
         sm[5] = tm.between(3, 4);
     }
+    admm_finish_stats(out);
+    if (timing && diag) {  // the selection Gram's rows actually processed
+        const double md = (double)sum_device_ints(s, rows + (size_t)4 * B1 * n, B1);
+        gram_timer.resolve(md * (p + 1) * 8 + (double)B1 * p * (p + 1) * 8, md * p * (p + 1) + 2.0 * md * p);
+    }
     if (diag) {
         diag->n_solves = (int64_t)B1 * R;
         diag->n_unconverged = out.unconverged;
@@ -341,7 +367,6 @@ static int var_fit(int T, int p, int d, const double *series, int block_len, con
     UOI_REQUIRE(nbt >= 1 && nbt < nblk, "estimation split leaves no training or evaluation block");
     UOI_REQUIRE((int64_t)o->B1 * o->q * p <= (int64_t)1 << 30, "too many solves");
     hipStream_t s = (hipStream_t)o->stream;
-    check_finite(s, series, (size_t)T * p, "series");
     const bool timing = (o->flags & UOI_FLAG_TIMING) != 0;
     float sm[8] = {0};
     if (diag) std::memset(diag->kstat, 0, sizeof(diag->kstat));
@@ -356,7 +381,8 @@ static int var_fit(int T, int p, int d, const double *series, int block_len, con
                       double *&u, int32_t *&its, double *&kkt, uint8_t *&flag, int32_t *&tr,
                       int32_t *&ev, int32_t *&ntr, int32_t *&nev, double *&GT, double *&CT,
                       double *&GE, double *&CE, double *&sE, void *&admm_w, void *&est_w, void *&cw) {
-        rows = a.take<int32_t>((size_t)4 * B1 * N + B1);  // draws, counts, distinct rows, weights, sizes
+        // draws, counts, distinct rows, weights, sizes, input check flag
+        rows = a.take<int32_t>((size_t)4 * B1 * N + B1 + 4);
         G = a.take<double>((size_t)B1 * p * p);
         C = a.take<double>((size_t)B1 * p * pe);
         lam = a.take<double>(q);
@@ -390,9 +416,11 @@ static int var_fit(int T, int p, int d, const double *series, int block_len, con
     A.base = (char *)pool_get(ar.off);
     layout(A, rows, G, C, lam, z, u, its, kkt, flag, tr, ev, ntr, nev, GT, CT, GE, CE, sE, admm_w, est_w,
            cw);
+    check_finite(s, rows + (size_t)4 * B1 * N + B1, {{series, (size_t)T * p, "series"}});
 
     const double *Xd = series, *Yd = series + p;  // regression row r: x = series[r], y = series[r+1]
     Timer tm(s, timing);
+    KernelTimer gram_timer(s, timing && diag ? &diag->kstat[UOI_KSTAT_GRAM] : nullptr);
     tm.mark();
     UOI_HIP(hipMemcpyAsync(lam, o->lambdas, sizeof(double) * q, hipMemcpyHostToDevice, s));
     launch_var_boot_rows(s, o->seed, B1, N, L, rows);
@@ -402,13 +430,9 @@ static int var_fit(int T, int p, int d, const double *series, int block_len, con
         int32_t *cntb = rows + (size_t)B1 * N, *drow = cntb + (size_t)B1 * N, *dw = drow + (size_t)B1 * N;
         int32_t *nd = dw + (size_t)B1 * N;
         launch_distinct_rows(s, B1, N, N, rows, cntb, drow, dw, nd);
-        KernelTimer kt(s, timing && diag ? &diag->kstat[UOI_KSTAT_GRAM] : nullptr);
+        gram_timer.start();
         launch_gram_f64_weighted(s, B1, N, drow, dw, nd, N, p, Xd, p, pe, Yd, p, G, C);
-        kt.stop();
-        if (timing && diag) {
-            const double md = (double)sum_device_ints(s, nd, B1);
-            kt.done(md * (p + pe) * 8 + (double)B1 * p * (p + pe) * 8, md * p * (p + 1) + 2.0 * md * p * pe);
-        }
+        gram_timer.stop();
     }
     tm.mark();
     P.G = G;
@@ -436,6 +460,12 @@ static int var_fit(int T, int p, int d, const double *series, int block_len, con
         sm[0] = tm.between(0, 1);
         sm[4] = tm.between(2, 3);
         sm[5] = tm.between(3, 4);
+    }
+    admm_finish_stats(out);
+    if (timing && diag) {
+        const double md = (double)sum_device_ints(s, rows + (size_t)4 * B1 * N, B1);
+        gram_timer.resolve(md * (p + pe) * 8 + (double)B1 * p * (p + pe) * 8,
+                           md * p * (p + 1) + 2.0 * md * p * pe);
     }
     if (diag) {
         diag->n_solves = (int64_t)B1 * R;
@@ -486,11 +516,12 @@ static int solve_batch(int nb, int p, const double *G, const double *c, const uo
         if (u0) transpose(s, nb, p, R, u0, u, false);
         else UOI_HIP(hipMemsetAsync(u, 0, sizeof(double) * nst, s));
     }
-    AdmmOut out{z, u, iters ? iters : its, kkt ? kkt : kk, 0, 0, nullptr, 0};
+    AdmmOut out{z, u, iters ? iters : its, kkt ? kkt : kk, 0, 0, nullptr, 0, nullptr};
     admm_solve(s, P, o->precision, o->solver, w, warm, out, nullptr);
     transpose(s, nb, p, R, z, z_out, true);
     if (u_out) transpose(s, nb, p, R, u, u_out, true);
     UOI_HIP(hipStreamSynchronize(s));
+    admm_finish_stats(out);
     return out.unconverged ? UOI_ENOCONV : UOI_OK;
 }
 
@@ -679,10 +710,11 @@ int uoi_lasso_solve_multi(int32_t nb, int32_t p, int32_t pe, const double *G, co
         layout(A, lam, z, u, its, kk, w);
         UOI_HIP(hipMemcpyAsync(lam, o->lambdas, sizeof(double) * q, hipMemcpyHostToDevice, s));
         P.lam = lam;
-        AdmmOut out{z, u, iters ? iters : its, kkt ? kkt : kk, 0, 0, nullptr, 0};
+        AdmmOut out{z, u, iters ? iters : its, kkt ? kkt : kk, 0, 0, nullptr, 0, nullptr};
         admm_solve(s, P, o->precision, o->solver, w, false, out, nullptr);
         transpose(s, nb, p, R, z, z_out, true);
         UOI_HIP(hipStreamSynchronize(s));
+        admm_finish_stats(out);
         return out.unconverged ? UOI_ENOCONV : UOI_OK;
     });
 }

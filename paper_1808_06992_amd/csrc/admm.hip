@@ -236,6 +236,24 @@ __global__ void k_freeze(int nb, int R, int pe, const double *__restrict__ vmax,
     if ((threadIdx.x & 63) == 0 && bal) atomicAdd(active, __popcll(bal));
 }
 
+__global__ void k_fill_i32(size_t n, int32_t v, int32_t *__restrict__ a) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
+// stat[0] += solves with a negative (unconverged) count, stat[1] = max count
+__global__ void k_iter_stats(int n, const int32_t *__restrict__ its, int *__restrict__ stat) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = i < n ? its[i] : 0;
+    const unsigned long long bal = __ballot(i < n && v < 0);
+    int m = v > 0 ? v : 0;
+    for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0) {
+        if (bal) atomicAdd(&stat[0], __popcll(bal));
+        if (m > 0) atomicMax(&stat[1], m);
+    }
+}
+
 template <typename T>
 __global__ void k_init_state(size_t n, const T *__restrict__ z0, const T *__restrict__ u0,
                              T *__restrict__ z, T *__restrict__ u, T *__restrict__ v) {
@@ -476,6 +494,7 @@ struct AdmmWork {
     double *M, *h, *cn, *vmax;
     uint8_t *state;
     int *active;
+    int *stat;  // [0] unconverged solves, [1] largest iteration count
     // float64 iteration buffers
     double *v0, *v1;
     // float32 phase
@@ -492,6 +511,7 @@ AdmmWork carve(const AdmmProblem &P, int precision, int solver, Arena &ar) {
     w.vmax = ar.take<double>((size_t)P.nb * P.R);
     w.state = ar.take<uint8_t>((size_t)P.nb * P.R);
     w.active = ar.take<int>(1 + P.nb);
+    w.stat = ar.take<int>(2);
     if (solver == UOI_SOLVER_BATCHED) {
         w.v0 = ar.take<double>(nst);
         w.v1 = ar.take<double>(nst);
@@ -514,11 +534,13 @@ size_t admm_work_bytes(const AdmmProblem &P, int precision, int solver) {
     return ar.off + spd_inverse_work_doubles(P.nb, P.p) * sizeof(double) + 4096;
 }
 
-// KKT evaluation of (a subset of) solves followed by the freeze step; returns the
-// number of solves still active.
+// KKT evaluation of (a subset of) solves followed by the freeze step, and an
+// asynchronous copy of the active counts ([0] all, [1 + b] per bootstrap) into
+// pinned host memory, marked by an event.
 template <typename T>
-static int check(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T *z, bool only_active,
-                 double park_tol, double stall_tol, int it, AdmmOut &out, std::vector<int> &act_b) {
+static void check_launch(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T *z,
+                         bool only_active, double park_tol, double stall_tol, int it, AdmmOut &out,
+                         int *hact, hipEvent_t ev) {
     UOI_HIP(hipMemsetAsync(w.vmax, 0, sizeof(double) * (size_t)P.nb * P.R, s));
     UOI_HIP(hipMemsetAsync(w.active, 0, sizeof(int) * (1 + P.nb), s));
     if (std::is_same<T, double>::value) {
@@ -542,63 +564,103 @@ static int check(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T
     hipLaunchKernelGGL(k_freeze, dim3(cdiv(ns, 256)), dim3(256), 0, s, P.nb, P.R, P.pe, w.vmax, w.cn,
                        P.tol, park_tol, stall_tol, it, w.state, out.iters, out.kkt, w.active);
     UOI_LAUNCH_CHECK();
-    act_b.resize(1 + P.nb);
-    UOI_HIP(hipMemcpyAsync(act_b.data(), w.active, sizeof(int) * (1 + P.nb), hipMemcpyDeviceToHost, s));
-    UOI_HIP(hipStreamSynchronize(s));
+    UOI_HIP(hipMemcpyAsync(hact, w.active, sizeof(int) * (1 + P.nb), hipMemcpyDeviceToHost, s));
+    UOI_HIP(hipEventRecord(ev, s));
+}
+
+static int check_wait(hipEvent_t ev, const int *hact, int nb, std::vector<int> &act_b) {
+    UOI_HIP(hipEventSynchronize(ev));
+    act_b.assign(hact, hact + 1 + nb);
     return act_b[0];
 }
 
+// ADMM iterations in chunks of check_every, each followed by a KKT check.  The
+// next chunk is queued before the host reads the previous check (it changes
+// only solves that the check left active), so the GPU does not idle while the
+// counts travel back; a chunk queued after the last solve froze does no work.
 template <typename T>
 static int sweep(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T *M, const T *h,
                  T *z, T *u, T *va, T *vb, int &it, int it_cap, double park_tol, double stall_tol,
                  AdmmOut &out) {
     std::vector<int> act_b;
-    int active = check<T>(s, P, w, z, true, park_tol, stall_tol, it, out, act_b);
+    int *hact = pinned_ints(1 + P.nb);
+    hipEvent_t ev;
+    UOI_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     uoi_kstat *ks = out.kstat ? &out.kstat[std::is_same<T, double>::value ? UOI_KSTAT_ADMM64
                                                                            : UOI_KSTAT_ADMM32]
                               : nullptr;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (ks) {
-        UOI_HIP(hipEventCreate(&e0));
-        UOI_HIP(hipEventCreate(&e1));
-    }
-    while (active > 0 && it < it_cap) {
-        int n = std::min(P.check_every, it_cap - it);
+    struct Pending {
+        hipEvent_t e0, e1;
+        double bytes, flops;
+        int n;
+        bool used;
+    };
+    std::vector<Pending> pend;
+    int itq = it;  // iterations queued so far
+    auto run_chunk = [&](int n) {
+        Pending pc{nullptr, nullptr, 0.0, 0.0, n, false};
         if (ks) {
-            // algorithmic traffic and work of one launch with the current active set
-            double by = 0.0, fl = 0.0;
-            for (int b = 0; b < P.nb; ++b)
-                if (act_b[1 + b] > 0) {
-                    by += (double)P.p * P.p * sizeof(T) + 4.0 * P.p * sizeof(T) * act_b[1 + b];
-                    fl += 2.0 * P.p * P.p * act_b[1 + b];
-                }
-            ks->bytes += by * n;
-            ks->flops += fl * n;
-            ks->launches += n;
-            UOI_HIP(hipEventRecord(e0, s));
+            UOI_HIP(hipEventCreate(&pc.e0));
+            UOI_HIP(hipEventCreate(&pc.e1));
+            UOI_HIP(hipEventRecord(pc.e0, s));
         }
         for (int t = 0; t < n; ++t) {
-            T *vin = (it & 1) ? vb : va;
-            T *vout = (it & 1) ? va : vb;
+            T *vin = (itq & 1) ? vb : va;
+            T *vout = (itq & 1) ? va : vb;
             UOI_DISPATCH_FN(P.R, {
                 AdmmEpi<T, 1, FN> epi{h, z, u, vout, w.state, P.lam, P.p, P.R, P.pe, (T)P.rho,
                                       (T)(1.0 / P.rho), (T)P.relax};
                 run_bgemm<T, 1, FN>(s, P.nb, P.p, P.R, M, vin, epi);
             });
-            ++it;
+            ++itq;
         }
-        if (ks) UOI_HIP(hipEventRecord(e1, s));
-        active = check<T>(s, P, w, z, true, park_tol, stall_tol, it, out, act_b);
-        if (ks) {
-            float ms = 0.f;
-            UOI_HIP(hipEventElapsedTime(&ms, e0, e1));
-            ks->ms += ms;
+        if (ks) UOI_HIP(hipEventRecord(pc.e1, s));
+        pend.push_back(pc);
+    };
+    // algorithmic traffic and work of a chunk run with the active set act_b
+    auto account = [&](Pending &pc) {
+        double by = 0.0, fl = 0.0;
+        for (int b = 0; b < P.nb; ++b)
+            if (act_b[1 + b] > 0) {
+                by += (double)P.p * P.p * sizeof(T) + 4.0 * P.p * sizeof(T) * act_b[1 + b];
+                fl += 2.0 * P.p * P.p * act_b[1 + b];
+            }
+        pc.bytes = by * pc.n;
+        pc.flops = fl * pc.n;
+        pc.used = true;
+    };
+    check_launch<T>(s, P, w, z, true, park_tol, stall_tol, it, out, hact, ev);
+    int active = check_wait(ev, hact, P.nb, act_b);
+    if (active > 0 && it < it_cap) {
+        run_chunk(std::min(P.check_every, it_cap - it));
+        account(pend.back());
+        it = itq;
+        for (;;) {
+            check_launch<T>(s, P, w, z, true, park_tol, stall_tol, it, out, hact, ev);
+            const bool spec = it < it_cap;
+            if (spec) run_chunk(std::min(P.check_every, it_cap - it));
+            active = check_wait(ev, hact, P.nb, act_b);
+            if (active == 0 || !spec) break;
+            account(pend.back());  // the queued chunk ran with this active set
+            it = itq;
         }
     }
     if (ks) {
-        UOI_HIP(hipEventDestroy(e0));
-        UOI_HIP(hipEventDestroy(e1));
+        if (!pend.empty()) UOI_HIP(hipEventSynchronize(pend.back().e1));
+        for (Pending &pc : pend) {
+            if (pc.used) {
+                float ms = 0.f;
+                UOI_HIP(hipEventElapsedTime(&ms, pc.e0, pc.e1));
+                ks->ms += ms;
+                ks->bytes += pc.bytes;
+                ks->flops += pc.flops;
+                ks->launches += pc.n;
+            }
+            UOI_HIP(hipEventDestroy(pc.e0));
+            UOI_HIP(hipEventDestroy(pc.e1));
+        }
     }
+    UOI_HIP(hipEventDestroy(ev));
     return active;
 }
 
@@ -625,11 +687,9 @@ void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, 
 
     UOI_HIP(hipMemsetAsync(w.state, 0, ns, s));
     UOI_HIP(hipMemsetAsync(out.kkt, 0x7f, sizeof(double) * ns, s));  // "previous" KKT: huge
-    {
-        std::vector<int32_t> neg(ns, -1);
-        UOI_HIP(hipMemcpyAsync(out.iters, neg.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, s));
-        UOI_HIP(hipStreamSynchronize(s));
-    }
+    hipLaunchKernelGGL(k_fill_i32, dim3(cdiv(ns, 256)), dim3(256), 0, s, (size_t)ns, -1, out.iters);
+    UOI_LAUNCH_CHECK();
+    out.dstat = w.stat;
     out.warm_used = 0;
     if (P.mlp) {
         // network start for every (bootstrap, lambda); falls back to cold per solve
@@ -742,17 +802,18 @@ void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, 
         UOI_HIP(hipEventElapsedTime(&stage_ms[1], ev[1], ev[2]));
         for (auto &e : ev) UOI_HIP(hipEventDestroy(e));
     }
-    UOI_HIP(hipStreamSynchronize(s));
-    // count unconverged solves and the largest iteration count
-    std::vector<int32_t> its(ns);
-    UOI_HIP(hipMemcpy(its.data(), out.iters, sizeof(int32_t) * ns, hipMemcpyDeviceToHost));
-    out.unconverged = 0;
-    out.max_iters = 0;
-    for (int v : its) {
-        if (v < 0) ++out.unconverged;
-        else out.max_iters = std::max(out.max_iters, v);
-    }
+    // unconverged solves and the largest iteration count, read by admm_finish_stats
+    UOI_HIP(hipMemsetAsync(w.stat, 0, 2 * sizeof(int), s));
+    hipLaunchKernelGGL(k_iter_stats, dim3(cdiv(ns, 256)), dim3(256), 0, s, ns, out.iters, w.stat);
+    UOI_LAUNCH_CHECK();
     (void)active;
+}
+
+void admm_finish_stats(AdmmOut &out) {
+    int h[2] = {0, 0};
+    if (out.dstat) UOI_HIP(hipMemcpy(h, out.dstat, sizeof(h), hipMemcpyDeviceToHost));
+    out.unconverged = h[0];
+    out.max_iters = h[1];
 }
 
 }  // namespace uoi

@@ -42,6 +42,9 @@ void set_last_error(const std::string &m);
 // ---------------------------------------------------------------------------
 void *pool_get(size_t bytes);  // returns a device buffer of at least `bytes`
 void pool_release();
+// Pinned host ints for asynchronous readbacks of small results (grow-only, one
+// buffer per device, like the pool; calls that overlap on one device race).
+int *pinned_ints(size_t n);
 
 struct Arena {
     char *base = nullptr;
@@ -244,11 +247,15 @@ struct AdmmOut {
     double *u;           // [nb][p][R]
     int32_t *iters;      // [nb*R]
     double *kkt;         // [nb*R]
-    int64_t unconverged;
+    int64_t unconverged; // set by admm_finish_stats once the stream has synchronised
     int max_iters;
     uoi_kstat *kstat;    // [UOI_KSTAT_N] accumulated when non-null (timing runs)
     int64_t warm_used;   // solves started from the network
+    int *dstat;          // device: [0] unconverged solves, [1] largest iteration count
 };
+// Reads the counts that admm_solve left in out.dstat (after the caller's final
+// synchronisation of the stream).
+void admm_finish_stats(AdmmOut &out);
 
 size_t admm_work_bytes(const AdmmProblem &P, int precision, int solver);
 void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, void *work,
