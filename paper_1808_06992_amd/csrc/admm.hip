@@ -187,14 +187,43 @@ __global__ void k_f64_to_f32(size_t n, const double *__restrict__ a, float *__re
     if (i < n) b[i] = (float)a[i];
 }
 
-// per-(b, e) ||c||_inf
-__global__ void k_cnorm(int p, int pe, const double *__restrict__ C, double *__restrict__ cn) {
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
-    int b = blockIdx.y;
-    if (e >= pe) return;
+// per-(b, e) ||c||_inf.  Block (64 columns e) x (4 row groups); with one column
+// all 256 threads share the rows.  Eight rows are loaded per step.
+__global__ __launch_bounds__(256) void k_cnorm(int p, int pe, const double *__restrict__ C,
+                                               double *__restrict__ cn) {
+    __shared__ double red[4][64];
+    const int b = blockIdx.y;
+    const double *Cb = C + (size_t)b * p * pe;
+    if (pe == 1) {
+        double m = 0.0;
+        for (int i0 = threadIdx.x; i0 < p; i0 += 2048) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = Cb[min(i0 + 256 * u, p - 1)];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) m = fmax(m, fabs(v[u]));  // clamped repeats do not change a max
+        }
+        m = wave_max(m);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][0] = m;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            cn[b] = fmax(fmax(red[0][0], red[1][0]), fmax(red[2][0], red[3][0]));
+        return;
+    }
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int e = min(blockIdx.x * 64 + tx, pe - 1);
     double m = 0.0;
-    for (int i = 0; i < p; ++i) m = fmax(m, fabs(C[((size_t)b * p + i) * pe + e]));
-    cn[(size_t)b * pe + e] = m;
+    for (int i0 = ty; i0 < p; i0 += 32) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = Cb[(size_t)min(i0 + 4 * u, p - 1) * pe + e];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) m = fmax(m, fabs(v[u]));
+    }
+    red[ty][tx] = m;
+    __syncthreads();
+    if (ty == 0 && blockIdx.x * 64 + tx < pe)
+        cn[(size_t)b * pe + blockIdx.x * 64 + tx] = fmax(fmax(red[0][tx], red[1][tx]), fmax(red[2][tx], red[3][tx]));
 }
 
 // After a KKT evaluation: freeze solves that meet the tolerance.
@@ -485,7 +514,7 @@ void launch_matmul_f64(hipStream_t s, int nb, int p, int R, const double *A, con
 }
 
 void launch_cnorm(hipStream_t s, int nb, int p, int pe, const double *C, double *cn) {
-    hipLaunchKernelGGL(k_cnorm, dim3(cdiv(pe, 64), nb), dim3(64), 0, s, p, pe, C, cn);
+    hipLaunchKernelGGL(k_cnorm, dim3(cdiv(pe, 64), nb), dim3(256), 0, s, p, pe, C, cn);
     UOI_LAUNCH_CHECK();
 }
 

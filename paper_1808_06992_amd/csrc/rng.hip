@@ -50,6 +50,39 @@ __global__ __launch_bounds__(256) void k_split_rank(uint64_t seed, uint32_t tag,
     if (i < cnt) is_train[(size_t)k * cnt + i] = before < ntrain ? 1 : 0;
 }
 
+// The same split for up to kSortMax items: one block per sample sorts the
+// (key, index) pairs in LDS (bitonic network) and flags the first ntrain.
+constexpr int kSortMax = 8192;
+__global__ __launch_bounds__(1024) void k_split_sort(uint64_t seed, uint32_t tag, int cnt, int np2,
+                                                     int ntrain, uint8_t *__restrict__ is_train) {
+    extern __shared__ unsigned long long sm[];
+    unsigned long long *key = sm;
+    int *ix = reinterpret_cast<int *>(sm + np2);
+    const int k = blockIdx.x;
+    for (int i = threadIdx.x; i < np2; i += blockDim.x) {
+        key[i] = i < cnt ? stream_key(seed, tag, k, i) : ~0ull;
+        ix[i] = i;
+    }
+    for (int size = 2; size <= np2; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            __syncthreads();
+            for (int t = threadIdx.x; t < (np2 >> 1); t += blockDim.x) {
+                const int i = 2 * t - (t & (stride - 1)), j = i + stride;
+                const bool up = (i & size) == 0;
+                const unsigned long long ki = key[i], kj = key[j];
+                const int ii = ix[i], ij = ix[j];
+                const bool gt = ki > kj || (ki == kj && ii > ij);
+                if (gt == up) {
+                    key[i] = kj; key[j] = ki;
+                    ix[i] = ij; ix[j] = ii;
+                }
+            }
+        }
+    __syncthreads();
+    for (int pos = threadIdx.x; pos < cnt; pos += blockDim.x)
+        is_train[(size_t)k * cnt + ix[pos]] = pos < ntrain ? 1 : 0;
+}
+
 // Stable compaction of items into ascending train / eval lists (one block per bootstrap).
 __global__ __launch_bounds__(256) void k_compact(int cnt, int ntrain, const uint8_t *__restrict__ is_train,
                                                  int32_t *__restrict__ train, int32_t *__restrict__ eval) {
@@ -211,8 +244,16 @@ void launch_var_boot_rows(hipStream_t s, uint64_t seed, int nb, int N, int L, in
 
 void launch_split(hipStream_t s, uint64_t seed, uint32_t tag, int nb, int cnt, int ntrain,
                   uint8_t *is_train) {
-    hipLaunchKernelGGL(k_split_rank, dim3(cdiv(cnt, 256), nb), dim3(256), 0, s, seed, tag, cnt,
-                       ntrain, is_train);
+    if (cnt <= kSortMax) {
+        int np2 = 2;
+        while (np2 < cnt) np2 <<= 1;
+        const size_t lds = (size_t)np2 * (sizeof(unsigned long long) + sizeof(int));
+        hipLaunchKernelGGL(k_split_sort, dim3(nb), dim3(1024), lds, s, seed, tag, cnt, np2, ntrain,
+                           is_train);
+    } else {
+        hipLaunchKernelGGL(k_split_rank, dim3(cdiv(cnt, 256), nb), dim3(256), 0, s, seed, tag, cnt,
+                           ntrain, is_train);
+    }
     UOI_LAUNCH_CHECK();
 }
 
