@@ -709,7 +709,7 @@ void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, 
     if (stage_ms) UOI_HIP(hipEventRecord(ev[0], s));
 
     // factor: M = (G + rho I)^{-1}, h = M C, and ||c||_inf per equation
-    spd_inverse_f64(s, P.nb, P.p, P.G, P.rho, w.M, spd_work);
+    spd_inverse_f64(s, P.nb, P.p, P.G, P.rho, w.M, spd_work, w.M32);  // M32: mixed only
     launch_matmul_f64(s, P.nb, P.p, P.pe, w.M, P.C, w.h);
     launch_cnorm(s, P.nb, P.p, P.pe, P.C, w.cn);
     if (stage_ms) UOI_HIP(hipEventRecord(ev[1], s));
@@ -802,8 +802,8 @@ void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, 
         // float32 phase: operator and state in float32, KKT in float64; solves that
         // reach kParkFactor x the tolerance, or stall within kStallFactor x the
         // tolerance, are parked and finished in float64.
-        size_t np2 = (size_t)P.nb * P.p * P.p, nh = (size_t)P.nb * P.p * P.pe;
-        hipLaunchKernelGGL(k_f64_to_f32, dim3(cdiv(np2, 256)), dim3(256), 0, s, np2, w.M, w.M32);
+        // (the float32 copy of M was written by the factorization)
+        size_t nh = (size_t)P.nb * P.p * P.pe;
         hipLaunchKernelGGL(k_f64_to_f32, dim3(cdiv(nh, 256)), dim3(256), 0, s, nh, w.h, w.h32);
         hipLaunchKernelGGL(k_f64_to_f32, dim3(cdiv(nst, 256)), dim3(256), 0, s, nst, out.z, w.z32);
         hipLaunchKernelGGL(k_f64_to_f32, dim3(cdiv(nst, 256)), dim3(256), 0, s, nst, out.u, w.u32);

@@ -205,9 +205,10 @@ void launch_train_from_eval(hipStream_t s, int nb, int n, int p, const double *X
                             int nt_c, int ne_c, const int32_t *nt, const int32_t *ne, double *GT,
                             double *CT, void *work);
 
-// Batched inverse of G + rho I by blocked Gauss-Jordan sweeps (writes M).
+// Batched inverse of G + rho I by blocked Gauss-Jordan sweeps (writes M, and
+// its float32 copy M32 when given).
 void spd_inverse_f64(hipStream_t s, int nb, int p, const double *G, double rho, double *M,
-                     double *work);
+                     double *work, float *M32 = nullptr);
 size_t spd_inverse_work_doubles(int nb, int p);
 
 // Batched products Y_b = A_b V_b with an epilogue (see gemm_epilogues in admm.hip).

@@ -11,7 +11,8 @@
 // an SPD matrix, so no pivoting is needed.
 //
 // Per 64-wide block step: (1) one workgroup per matrix sweeps the pivot block
-// in registers (Q = A_KK^{-1}); (2) a row-parallel MFMA kernel forms W = A_:K Q
+// in registers (Q = A_KK^{-1}), inside the previous step's update after the
+// first step; (2) a row-parallel MFMA kernel forms W = A_:K Q
 // and keeps the old panel A_:K, both stored pivot-index-major; (3) an MFMA kernel
 // applies the rank-64 update to the 64x64 tiles on and below the diagonal (the
 // sweep keeps A symmetric).  The first step reads G and adds rho on the
@@ -88,19 +89,18 @@ __global__ __launch_bounds__(256) void k_inv_small(int p, const double *__restri
     for (int e = threadIdx.x; e < p * p; e += 256) Mb[e] = -A[e];
 }
 
-// (1) Q = A_KK^{-1} of the pivot block [k0, k0+kb), one workgroup per matrix.
-// Thread (ty, tx) = (tid / 64, tid % 64) keeps rows ty + 4a (a < 16) of column
-// tx in registers for all 64 steps (the block is padded with the identity
-// beyond kb, which leaves the kb x kb part unchanged); step k publishes the old
-// pivot row and column through LDS, double-buffered by step parity so that one
-// barrier per step suffices.  LDS reads are broadcasts or unit-stride.
-// The first block step reads G and adds the shift rho on the diagonal.
-__global__ __launch_bounds__(256) void k_pivot(int p, int k0, int kb, const double *__restrict__ src,
-                                               double shift, double *__restrict__ Q) {
+// (1) Q = A_KK^{-1} of the pivot block [k0, k0+kb) of one matrix, by one
+// workgroup of 256 threads.  Thread (ty, tx) = (tid / 64, tid % 64) keeps rows
+// ty + 4a (a < 16) of column tx in registers for all 64 steps (the block is
+// padded with the identity beyond kb, which leaves the kb x kb part unchanged);
+// step k publishes the old pivot row and column through LDS, double-buffered
+// by step parity so that one barrier per step suffices.  LDS reads are
+// broadcasts or unit-stride.  The first block step reads G and adds the shift
+// rho on the diagonal.
+__device__ void pivot_block(int p, int k0, int kb, const double *__restrict__ Ab, double shift,
+                            double *__restrict__ Qb) {
     __shared__ double rowb[2][NB], colb[2][NB];
-    const int b = blockIdx.x;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    const double *Ab = src + (size_t)b * p * p;
     double v[16];
 #pragma unroll
     for (int a = 0; a < 16; ++a) {  // loads from clamped addresses, all in flight together
@@ -135,12 +135,18 @@ __global__ __launch_bounds__(256) void k_pivot(int p, int k0, int kb, const doub
             v[a] = nv;
         }
     }
-    double *Qb = Q + (size_t)b * NB * NB;
 #pragma unroll
     for (int a = 0; a < 16; ++a) {
         const int i = ty + 4 * a;
         Qb[i * NB + tx] = (i < kb && tx < kb) ? -v[a] : 0.0;  // zero padded
     }
+}
+
+// The first pivot block (later ones are inverted inside the preceding update).
+__global__ __launch_bounds__(256) void k_pivot(int p, int k0, int kb, const double *__restrict__ src,
+                                               double shift, double *__restrict__ Q) {
+    const int b = blockIdx.x;
+    pivot_block(p, k0, kb, src + (size_t)b * p * p, shift, Q + (size_t)b * NB * NB);
 }
 
 // (2) Panel for rows [i0, i0+64): Old = A[i, K] and W = A[i, K] Q (MFMA), both
@@ -238,9 +244,34 @@ __global__ __launch_bounds__(256) void k_update(int p, int k0, int kb, const dou
                                                 double shift, double *__restrict__ dst,
                                                 const double *__restrict__ Wt,
                                                 const double *__restrict__ Ot,
-                                                const double *__restrict__ Q) {
-    int tile, by0, b;
-    xcd_tile(tile, by0, b);  // all tiles of one matrix on one XCD: the panels stay in its L2
+                                                const double *__restrict__ Q,
+                                                double *__restrict__ Qnext) {
+    // Workgroup -> (matrix, tile).  When another pivot block follows, the first nb
+    // workgroups (dispatched first) take the diagonal tile of that block, one per
+    // matrix, and invert it once stored, while the other tiles are updated.  The
+    // remaining tiles are dealt so that all tiles of one matrix run on the same
+    // XCD: the panels then stay in its L2.
+    const int ntri = gridDim.x, nb = gridDim.z;
+    const int L = blockIdx.x + ntri * blockIdx.z;
+    const int kt = k0 / 64;
+    const bool next = k0 + NB < p;
+    const int dtile = (kt + 1) * (kt + 2) / 2 + kt + 1;  // tile index of (kt+1, kt+1)
+    int tile, b;
+    bool pivot = false;
+    if (!next) {
+        const int id = xcd_remap(L, nb * ntri);
+        b = id / ntri;
+        tile = id - b * ntri;
+    } else if (L < nb) {
+        b = L;
+        tile = dtile;
+        pivot = true;
+    } else {
+        const int id = xcd_remap(L - nb, nb * (ntri - 1));
+        b = id / (ntri - 1);
+        tile = id - b * (ntri - 1);
+        tile += tile >= dtile;
+    }
     int ti = (int)((sqrt(8.0 * tile + 1.0) - 1.0) * 0.5);
     while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
     while (ti * (ti + 1) / 2 > tile) --ti;
@@ -285,7 +316,6 @@ __global__ __launch_bounds__(256) void k_update(int p, int k0, int kb, const dou
     }
     double *Db = dst + (size_t)b * p * p;
     const double *Qb = Q + (size_t)b * NB * NB;
-    const int kt = k0 / 64;
     const bool plain = ti != kt && tj != kt;
 #pragma unroll
     for (int fm = 0; fm < 2; ++fm)
@@ -304,17 +334,23 @@ __global__ __launch_bounds__(256) void k_update(int p, int k0, int kb, const dou
                 }
                 Db[(size_t)i * p + j] = v;
             }
+    if (pivot) {
+        __syncthreads();  // the tile's stores are visible to the whole workgroup
+        pivot_block(p, k0 + NB, min(NB, p - k0 - NB), Db, 0.0, Qnext + (size_t)b * NB * NB);
+    }
 }
 
 // (4) M = -(swept matrix), with the upper triangle filled from the lower one:
 // 32x32 tiles on or below the diagonal are read through LDS and written to
-// both positions (diagonal tiles from their lower triangle only).
-__global__ void k_symneg(int p, double *__restrict__ M) {
+// both positions (diagonal tiles from their lower triangle only).  When M32 is
+// given, the float32 copy of M is written in the same pass.
+__global__ void k_symneg(int p, double *__restrict__ M, float *__restrict__ M32) {
     __shared__ double t[32][33];
     const int b = blockIdx.z;
     const int bi = blockIdx.y, bj = blockIdx.x;
     if (bj > bi) return;
     double *Mb = M + (size_t)b * p * p;
+    float *Fb = M32 ? M32 + (size_t)b * p * p : nullptr;
     const int tx = threadIdx.x, ty = threadIdx.y;
     double v[4];
 #pragma unroll
@@ -327,42 +363,60 @@ __global__ void k_symneg(int p, double *__restrict__ M) {
     __syncthreads();
     for (int r = ty; r < 32; r += 8) {
         const int i = bi * 32 + r, j = bj * 32 + tx;      // lower position
-        if (i < p && j < p && (bi > bj || r >= tx)) Mb[(size_t)i * p + j] = -t[r][tx];
+        if (i < p && j < p && (bi > bj || r >= tx)) {
+            Mb[(size_t)i * p + j] = -t[r][tx];
+            if (Fb) Fb[(size_t)i * p + j] = (float)-t[r][tx];
+        }
         const int i2 = bj * 32 + r, j2 = bi * 32 + tx;    // upper position (i2, j2) = (j, i)
-        if (i2 < p && j2 < p && (bi > bj || tx > r)) Mb[(size_t)i2 * p + j2] = -t[tx][r];
+        if (i2 < p && j2 < p && (bi > bj || tx > r)) {
+            Mb[(size_t)i2 * p + j2] = -t[tx][r];
+            if (Fb) Fb[(size_t)i2 * p + j2] = (float)-t[tx][r];
+        }
     }
+}
+
+__global__ void k_narrow(size_t n, const double *__restrict__ a, float *__restrict__ b) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (float)a[i];
 }
 
 size_t spd_inverse_work_doubles(int nb, int p) {
     if (p <= SMALL) return 0;
-    return (size_t)nb * NB * NB + 2 * (size_t)nb * p * NB;
+    return 2 * (size_t)nb * NB * NB + 2 * (size_t)nb * p * NB;
 }
 
 void spd_inverse_f64(hipStream_t s, int nb, int p, const double *G, double rho, double *M,
-                     double *work) {
+                     double *work, float *M32) {
     if (p <= SMALL) {
         size_t lds = sizeof(double) * (size_t)p * p;
         hipLaunchKernelGGL(k_inv_small, dim3(nb), dim3(256), lds, s, p, G, rho, M);
+        if (M32) {
+            const size_t n = (size_t)nb * p * p;
+            hipLaunchKernelGGL(k_narrow, dim3(cdiv(n, 256)), dim3(256), 0, s, n, M, M32);
+        }
         UOI_LAUNCH_CHECK();
         return;
     }
-    double *Q = work;
-    double *Wt = Q + (size_t)nb * NB * NB;
+    // Q of step K lives in buffer K % 2: the update of step K inverts the next
+    // pivot block into the other buffer while its own tiles still read Q.
+    double *Qbuf[2] = {work, work + (size_t)nb * NB * NB};
+    double *Wt = work + 2 * (size_t)nb * NB * NB;
     double *Ot = Wt + (size_t)nb * p * NB;
     const int T = (int)cdiv(p, 64);
-    for (int k0 = 0; k0 < p; k0 += NB) {
+    hipLaunchKernelGGL(k_pivot, dim3(nb), dim3(256), 0, s, p, 0, std::min(NB, p), G, rho, Qbuf[0]);
+    for (int k0 = 0, K = 0; k0 < p; k0 += NB, ++K) {
         const int kb = std::min(NB, p - k0);
         // the first step reads G + rho I and writes every lower tile of M
         const double *src = k0 == 0 ? G : M;
         const double sh = k0 == 0 ? rho : 0.0;
-        hipLaunchKernelGGL(k_pivot, dim3(nb), dim3(256), 0, s, p, k0, kb, src, sh, Q);
+        double *Q = Qbuf[K & 1];
         hipLaunchKernelGGL(k_panel, dim3(T, nb), dim3(256), 0, s, p, k0, kb, src, sh, Q, Wt, Ot);
         hipLaunchKernelGGL(k_update, dim3(T * (T + 1) / 2, 1, nb), dim3(256), 0, s, p, k0, kb, src, sh, M,
-                           Wt, Ot, Q);
+                           Wt, Ot, Q, Qbuf[(K + 1) & 1]);
         UOI_LAUNCH_CHECK();
     }
     const int T32 = (int)cdiv(p, 32);
-    hipLaunchKernelGGL(k_symneg, dim3(T32, T32, nb), dim3(32, 8), 0, s, p, M);
+    hipLaunchKernelGGL(k_symneg, dim3(T32, T32, nb), dim3(32, 8), 0, s, p, M, M32);
     UOI_LAUNCH_CHECK();
 }
 

@@ -84,14 +84,17 @@ def test_gram_var_parity(api, orc):
 
 # --------------------------------------------------------------------------- inverse
 
-@pytest.mark.parametrize("p", [1, 7, 50, 88, 89, 130, 200])
-def test_spd_inverse_parity(api, orc, p):
+@pytest.mark.parametrize("p,nb", [(1, 2), (7, 2), (50, 2), (88, 2), (89, 2), (130, 2), (200, 2),
+                                  (257, 11)])
+def test_spd_inverse_parity(api, orc, p, nb):
+    """Blocked sweeps with a ragged last pivot block (p = 257: one column), and a
+    batch that is not a multiple of the 8 XCDs."""
     rng = np.random.default_rng(p)
     n = 3 * p + 10
     X = rng.standard_normal((n, p))
-    G = np.stack([orc.gram(X, X[:, 0], orc.boot_rows(1, k, n))[0] for k in range(2)])
+    G = np.stack([orc.gram(X, X[:, 0], orc.boot_rows(1, k, n))[0] for k in range(nb)])
     M = api.spd_inverse(cuda(G), 1.0).cpu().numpy()
-    for b in range(2):
+    for b in range(nb):
         ref = np.linalg.inv(G[b] + np.eye(p))
         np.testing.assert_allclose(M[b], ref, rtol=1e-11, atol=1e-13 * np.abs(ref).max())
 
