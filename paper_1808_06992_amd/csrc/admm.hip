@@ -115,6 +115,101 @@ struct AdmmEpi {
     }
 };
 
+// The same iteration in float32 for the split-bfloat16 product: v' = z - u is
+// written as the three bfloat16 planes Vp[b][part][r][i] (parts as in
+// split_bf16x3; rows i >= p are never written and stay zero).  A lane holds four
+// consecutive rows i of one column r, so each part is one 8-byte store.
+template <int FN>
+struct AdmmEpiBf3 {
+    const float *h;      // [nb][p][pe]
+    float *z, *u;        // [nb][p][R]
+    __bf16 *vp;          // [nb][3][R][ldk]
+    const uint8_t *state;
+    const double *lam;
+    int p, R, pe, ldk;
+    float rho, inv_rho, alpha;
+    __device__ bool tile_active(int b, int r0, int w) const {
+        const int lane = threadIdx.x & 63, r = r0 + lane;
+        const bool a = lane < w && r < R && state[(size_t)b * R + min(r, R - 1)] == 0;
+        return __ballot(a) != 0ull;
+    }
+    template <class Acc>
+    __device__ void apply(int b, int i_base, int r0, int lr, int lk, Acc (&acc)[1][FN]) const {
+        float hv[FN][4], uv[FN][4], zv[FN][4], thr[FN];
+        const bool relaxed = alpha != 1.0f;
+        bool act[FN];
+        int rc[FN];
+#pragma unroll
+        for (int c = 0; c < FN; ++c) {
+            const int r = r0 + 16 * c + lr;
+            rc[c] = min(r, R - 1);
+            act[c] = r < R && state[(size_t)b * R + rc[c]] == 0;
+            thr[c] = (float)lam[rc[c] / pe] * inv_rho;
+        }
+        const int i4 = i_base + 4 * lk;  // rows i4 .. i4 + 3 of this lane
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int ic = min(i4 + t, p - 1);
+#pragma unroll
+            for (int c = 0; c < FN; ++c) {
+                const size_t o = ((size_t)b * p + ic) * R + rc[c];
+                uv[c][t] = u[o];
+                zv[c][t] = relaxed ? z[o] : 0.0f;
+                hv[c][t] = h[((size_t)b * p + ic) * pe + rc[c] % pe];
+            }
+        }
+        const size_t plane = (size_t)R * ldk;
+#pragma unroll
+        for (int c = 0; c < FN; ++c) {
+            if (!act[c]) continue;
+            const int r = r0 + 16 * c + lr;
+            float vv[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int i = i4 + t;
+                float x = hv[c][t] + rho * acc[0][c][t];
+                if (relaxed) x = alpha * x + (1.0f - alpha) * zv[c][t];
+                const float uo = uv[c][t];
+                const float zn = soft_threshold(x + uo, thr[c]);
+                const float un = uo + x - zn;
+                vv[t] = zn - un;
+                if (i < p) {
+                    const size_t o = ((size_t)b * p + i) * R + r;
+                    z[o] = zn;
+                    u[o] = un;
+                }
+            }
+            __bf16 *dst = vp + (size_t)b * 3 * plane + (size_t)r * ldk + i4;
+            if (i4 + 3 < p) {
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    typedef __bf16 bfx4 __attribute__((ext_vector_type(4)));
+                    bfx4 w;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const __bf16 a1 = (__bf16)vv[t];
+                        const float r1 = vv[t] - (float)a1;
+                        const __bf16 a2 = (__bf16)r1;
+                        w[t] = q == 0 ? a1 : (q == 1 ? a2 : (__bf16)(r1 - (float)a2));
+                    }
+                    *(bfx4 *)(dst + q * plane) = w;
+                }
+            } else {
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    if (i4 + t < p) {
+                        const __bf16 a1 = (__bf16)vv[t];
+                        const float r1 = vv[t] - (float)a1;
+                        const __bf16 a2 = (__bf16)r1;
+                        dst[t] = a1;
+                        dst[plane + t] = a2;
+                        dst[2 * plane + t] = (__bf16)(r1 - (float)a2);
+                    }
+            }
+        }
+    }
+};
+
 // --- epilogue: KKT residual --------------------------------------------------
 // acc = (G z)_i; g = c_i - acc; v_i as in the KKT definition; per-solve max over
 // i is reduced in the wave and then with an atomic max on the bit pattern.
@@ -305,6 +400,28 @@ __global__ void k_refresh_v(size_t n, const T *__restrict__ z, const T *__restri
         v0[i] = d;
         v1[i] = d;
     }
+}
+
+// v = z - u as the bfloat16 planes of the split product, in both buffers
+__global__ void k_refresh_vp(int nb, int p, int R, int ldk, const float *__restrict__ z,
+                             const float *__restrict__ u, __bf16 *__restrict__ v0,
+                             __bf16 *__restrict__ v1) {
+    const size_t n = (size_t)nb * R * p;
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const int i = (int)(e % p);  // row fastest: the plane stores are contiguous
+    const size_t br = e / p;
+    const int r = (int)(br % R), b = (int)(br / R);
+    const size_t o = ((size_t)b * p + i) * R + r;
+    const float d = z[o] - u[o];
+    const __bf16 a1 = (__bf16)d;
+    const float r1 = d - (float)a1;
+    const __bf16 a2 = (__bf16)r1;
+    const __bf16 a3 = (__bf16)(r1 - (float)a2);
+    const size_t plane = (size_t)R * ldk;
+    const size_t q = (size_t)b * 3 * plane + (size_t)r * ldk + i;
+    v0[q] = a1; v0[q + plane] = a2; v0[q + 2 * plane] = a3;
+    v1[q] = a1; v1[q + plane] = a2; v1[q + 2 * plane] = a3;
 }
 
 __global__ void k_unpark(size_t n, uint8_t *__restrict__ state) {
@@ -527,7 +644,8 @@ struct AdmmWork {
     // float64 iteration buffers
     double *v0, *v1;
     // float32 phase
-    float *M32, *h32, *z32, *u32, *w0, *w1;
+    float *M32, *h32, *z32, *u32;
+    __bf16 *vp0, *vp1;  // float32 phase: v as bfloat16 planes [nb][3][R][ldk]
     double *z64tmp;
 };
 
@@ -549,8 +667,9 @@ AdmmWork carve(const AdmmProblem &P, int precision, int solver, Arena &ar) {
             w.h32 = ar.take<float>((size_t)P.nb * P.p * P.pe);
             w.z32 = ar.take<float>(nst);
             w.u32 = ar.take<float>(nst);
-            w.w0 = ar.take<float>(nst);
-            w.w1 = ar.take<float>(nst);
+            const size_t np3 = (size_t)P.nb * 3 * P.R * bf3_ldk(P.p);
+            w.vp0 = ar.take<__bf16>(np3);
+            w.vp1 = ar.take<__bf16>(np3);
         }
     }
     return w;
@@ -637,9 +756,17 @@ static int sweep(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T
             T *vin = (itq & 1) ? vb : va;
             T *vout = (itq & 1) ? va : vb;
             UOI_DISPATCH_FN(P.R, {
-                AdmmEpi<T, 1, FN> epi{h, z, u, vout, w.state, P.lam, P.p, P.R, P.pe, (T)P.rho,
-                                      (T)(1.0 / P.rho), (T)P.relax};
-                run_bgemm<T, 1, FN>(s, P.nb, P.p, P.R, M, vin, epi);
+                if constexpr (std::is_same<T, float>::value) {
+                    __bf16 *pin = (itq & 1) ? w.vp1 : w.vp0;
+                    __bf16 *pout = (itq & 1) ? w.vp0 : w.vp1;
+                    AdmmEpiBf3<FN> epi{h, z, u, pout, w.state, P.lam, P.p, P.R, P.pe, bf3_ldk(P.p),
+                                       (float)P.rho, (float)(1.0 / P.rho), (float)P.relax};
+                    run_bgemm_bf3<FN>(s, P.nb, P.p, P.R, M, pin, epi);
+                } else {
+                    AdmmEpi<T, 1, FN> epi{h, z, u, vout, w.state, P.lam, P.p, P.R, P.pe, (T)P.rho,
+                                          (T)(1.0 / P.rho), (T)P.relax};
+                    run_bgemm<T, 1, FN>(s, P.nb, P.p, P.R, M, vin, epi);
+                }
             });
             ++itq;
         }
@@ -807,10 +934,15 @@ void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, 
         hipLaunchKernelGGL(k_f64_to_f32, dim3(cdiv(nh, 256)), dim3(256), 0, s, nh, w.h, w.h32);
         hipLaunchKernelGGL(k_f64_to_f32, dim3(cdiv(nst, 256)), dim3(256), 0, s, nst, out.z, w.z32);
         hipLaunchKernelGGL(k_f64_to_f32, dim3(cdiv(nst, 256)), dim3(256), 0, s, nst, out.u, w.u32);
-        hipLaunchKernelGGL(k_refresh_v<float>, dim3(cdiv(nst, 256)), dim3(256), 0, s, nst, w.z32,
-                           w.u32, w.w0, w.w1);
+        // v planes: zero (rows past p stay zero), then v = z - u
+        const int ldk = bf3_ldk(P.p);
+        const size_t np3 = (size_t)P.nb * 3 * P.R * ldk;
+        UOI_HIP(hipMemsetAsync(w.vp0, 0, sizeof(__bf16) * np3, s));
+        UOI_HIP(hipMemsetAsync(w.vp1, 0, sizeof(__bf16) * np3, s));
+        hipLaunchKernelGGL(k_refresh_vp, dim3(cdiv(nst, 256)), dim3(256), 0, s, P.nb, P.p, P.R, ldk, w.z32,
+                           w.u32, w.vp0, w.vp1);
         UOI_LAUNCH_CHECK();
-        active = sweep<float>(s, P, w, w.M32, w.h32, w.z32, w.u32, w.w0, w.w1, it, P.max_iter,
+        active = sweep<float>(s, P, w, w.M32, w.h32, w.z32, w.u32, nullptr, nullptr, it, P.max_iter,
                               P.tol * kParkFactor, P.tol * kStallFactor, out);
         // widen the state and finish parked / active solves in float64
         hipLaunchKernelGGL(k_f32_to_f64, dim3(cdiv(nst, 256)), dim3(256), 0, s, nst, w.z32, out.z);

@@ -141,6 +141,188 @@ inline void run_bgemm(hipStream_t s, int nb, int p, int R, const T *A, const T *
     UOI_LAUNCH_CHECK();
 }
 
+// ---------------------------------------------------------------------------
+// Float32 product on bfloat16 MFMA (16x16x32).  Every float32 operand x is
+// split as x = x1 + x2 + x3 + r, each part the bfloat16 rounding (to nearest)
+// of what the previous parts leave, so |x2| <= 2^-8 |x|, |x3| <= 2^-16 |x| and
+// |r| <= 2^-24 |x|; the differences are exact in float32.  The six part
+// products of order 2^-16 and above (a1b1, a1b2, a2b1, a1b3, a2b2, a3b1) give A V
+// to float32 accuracy: the dropped ones are below 2^-23 relative.  bfloat16
+// keeps the float32 exponent range, so no scaling is needed.  The six MFMAs of
+// a 32-deep step cost about a third of the eight float32 16x16x4 steps they
+// replace, which leaves the float32 ADMM iteration bound by reading A.
+//
+// Layout as k_bgemm (4 waves x 16 rows, 16*FN columns, KC = 32): lane (lr, lk)
+// reads eight entries of row i = i_base + lr of A (= column i, by symmetry) as
+// two 16-byte loads and splits them in registers.  V arrives
+// already split, as three bfloat16 planes Vp[b][part][r][k] with k contiguous
+// and rows k >= p zero up to bf3_ldk(p) (the producing epilogue writes them; it
+// splits each element once instead of once per row block); a chunk is copied to
+// LDS (double buffered) in 16-byte pieces, so that each MFMA operand is one
+// 16-byte LDS read.
+typedef __bf16 bfx8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ void split_bf16x3(const float (&x)[8], bfx8 &p1, bfx8 &p2, bfx8 &p3) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const __bf16 a = (__bf16)x[e];
+        const float r1 = x[e] - (float)a;
+        const __bf16 b = (__bf16)r1;
+        const float r2 = r1 - (float)b;
+        p1[e] = a;
+        p2[e] = b;
+        p3[e] = (__bf16)r2;
+    }
+}
+
+constexpr int BF3_KC = 32;  // k per chunk
+constexpr int BF3_D = 4;    // register ring depth (chunks in flight)
+// k extent of a V plane row: the chunks the product reads, rounded to the ring
+inline int bf3_ldk(int p) {
+    const int nchunk = (p + BF3_KC - 1) / BF3_KC;
+    return ((nchunk + BF3_D - 1) / BF3_D * BF3_D + BF3_D) * BF3_KC;
+}
+
+__device__ __forceinline__ fx4 mfma16x16x32(bfx8 a, bfx8 b, fx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+template <int FN, bool VEC4, class Epi>
+__global__ __launch_bounds__(256) void k_bgemm_bf3(int p, int R, const float *__restrict__ A,
+                                                   const __bf16 *__restrict__ Vp, int ldk, Epi epi) {
+    constexpr int TN = 16 * FN;
+    constexpr int KC = BF3_KC;
+    constexpr int KP = KC + 8;  // k stride of an LDS plane row (bfloat16), 16-byte aligned
+    __shared__ __attribute__((aligned(16))) __bf16 Vs[2][3][TN][KP];
+    int bx, by, b;
+    xcd_tile(bx, by, b);
+    const int r0 = bx * TN;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wid = tid >> 6;
+    const int i_base = by * 64 + wid * 16;
+    const int lr = lane & 15, lk = lane >> 4;
+    if (!epi.tile_active(b, r0, TN)) return;  // uniform over the workgroup
+
+    const float *Ab = A + (size_t)b * p * p;
+    fx4 acc[1][FN];
+#pragma unroll
+    for (int c = 0; c < FN; ++c) acc[0][c] = fx4{0.f, 0.f, 0.f, 0.f};
+
+    // All loads come from valid addresses: the V planes hold zeros at rows p ..
+    // ldk - 1, which cancel the clamped A values they meet; rows of A past p and
+    // columns past R only reach outputs that the epilogue discards.
+    // The loop body has no branch around a load: the compiler can then keep the
+    // loads of several chunks in flight (a load under a branch makes it wait for
+    // every earlier one).
+    const float *arow = Ab + (size_t)min(i_base + lr, p - 1) * p;
+    // Lane group lk takes k = 4 lk .. 4 lk + 3 and 16 + 4 lk .. 16 + 4 lk + 3 of a
+    // chunk (elements 0-3 and 4-7 of its MFMA operand), so that each of the two
+    // loads covers 64 contiguous bytes of a row; V is laid out in LDS in the same
+    // order.
+    auto load_a = [&](float (&an)[8], int k0) {
+        const int k = k0 + 4 * lk;
+        if (VEC4) {  // rows of A 16-byte aligned (p % 4 == 0)
+            const fx4 x0 = *(const fx4 *)(arow + min(k, p - 4));
+            const fx4 x1 = *(const fx4 *)(arow + min(k + 16, p - 4));
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                an[e] = x0[e];
+                an[4 + e] = x1[e];
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                an[e] = arow[min(k + e, p - 1)];
+                an[4 + e] = arow[min(k + 16 + e, p - 1)];
+            }
+        }
+    };
+    // V: thread tid < 4 TN copies rows k0 + 8 og .. + 7 of tile column cv, three
+    // planes (the four threads of a column read its 64 contiguous bytes); the
+    // other threads load a copy and store nothing
+    const bool vst = tid < 4 * TN;
+    const int cv = min(tid >> 2, TN - 1), og = tid & 3;
+    const size_t plane = (size_t)R * ldk;
+    const __bf16 *vcol = Vp + (size_t)b * 3 * plane + (size_t)min(r0 + cv, R - 1) * ldk + 8 * og;
+    typedef bfx8 vraw[3];
+    auto load_v = [&](vraw &vn, int k0) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) vn[q] = *(const bfx8 *)(vcol + q * plane + k0);
+    };
+    // rows 8 og .. 8 og + 3 and 8 og + 4 .. 8 og + 7 go to the operand positions
+    // of the lane groups that take them (see load_a)
+    const int s0 = 8 * ((2 * og) & 3) + 4 * (og >> 1);
+    auto store_v = [&](int buf, const vraw &vn) {
+        if (vst) {
+            typedef __bf16 bfx4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                *(bfx4 *)&Vs[buf][q][cv][s0] = bfx4{vn[q][0], vn[q][1], vn[q][2], vn[q][3]};
+                *(bfx4 *)&Vs[buf][q][cv][s0 + 8] = bfx4{vn[q][4], vn[q][5], vn[q][6], vn[q][7]};
+            }
+        }
+    };
+
+    // Raw chunks travel through a register ring D deep: the loads of chunk c + D
+    // are issued when chunk c is multiplied, so memory latency is covered by D - 1
+    // chunks of work (the MFMAs alone are too short to cover it).  The chunk loop
+    // is unrolled by D so that ring slots are static registers, and runs over a
+    // multiple of D chunks: chunks past p are staged as zeros.
+    constexpr int D = BF3_D;
+    const int nchunk = (p + KC - 1) / KC;
+    float an[D][8];
+    vraw vn[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        load_v(vn[d], d * KC);
+        load_a(an[d], d * KC);
+    }
+    bfx8 a1, a2, a3;
+    store_v(0, vn[0]);
+    split_bf16x3(an[0], a1, a2, a3);
+    __syncthreads();
+    for (int c = 0; c < nchunk; c += D) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const int cc = c + d;
+            // slot d was staged at the end of the previous chunk
+            load_v(vn[d], (cc + D) * KC);
+            load_a(an[d], (cc + D) * KC);
+            const int cur = cc & 1;
+#pragma unroll
+            for (int q = 0; q < FN; ++q) {
+                const bfx8 b1 = *(const bfx8 *)&Vs[cur][0][16 * q + lr][8 * lk];
+                const bfx8 b2 = *(const bfx8 *)&Vs[cur][1][16 * q + lr][8 * lk];
+                const bfx8 b3 = *(const bfx8 *)&Vs[cur][2][16 * q + lr][8 * lk];
+                fx4 t = acc[0][q];
+                t = mfma16x16x32(a3, b1, t);  // small terms first
+                t = mfma16x16x32(a2, b2, t);
+                t = mfma16x16x32(a1, b3, t);
+                t = mfma16x16x32(a2, b1, t);
+                t = mfma16x16x32(a1, b2, t);
+                acc[0][q] = mfma16x16x32(a1, b1, t);
+            }
+            store_v(cur ^ 1, vn[(d + 1) % D]);
+            split_bf16x3(an[(d + 1) % D], a1, a2, a3);
+            __syncthreads();
+        }
+    }
+    if (i_base < p) epi.apply(b, i_base, r0, lr, lk, acc);
+}
+
+// Vp: three bfloat16 planes [nb][3][R][ldk], ldk = bf3_ldk(p), zero at rows >= p.
+template <int FN, class Epi>
+inline void run_bgemm_bf3(hipStream_t s, int nb, int p, int R, const float *A, const __bf16 *Vp,
+                          const Epi &epi) {
+    dim3 grid(cdiv(R, 16 * FN), cdiv(p, 64), nb);
+    const int ldk = bf3_ldk(p);
+    if (p % 4 == 0 && ((uintptr_t)A & 15) == 0)
+        hipLaunchKernelGGL((k_bgemm_bf3<FN, true, Epi>), grid, dim3(256), 0, s, p, R, A, Vp, ldk, epi);
+    else
+        hipLaunchKernelGGL((k_bgemm_bf3<FN, false, Epi>), grid, dim3(256), 0, s, p, R, A, Vp, ldk, epi);
+    UOI_LAUNCH_CHECK();
+}
+
 // Column-block width: the smallest multiple of 16 that covers R, up to 64.
 #define UOI_DISPATCH_FN(R, ...)                                   \
     do {                                                          \
