@@ -257,9 +257,10 @@ static int lasso_fit(int n, int p, const double *X, const double *y, const uoi_o
     auto layout = [&](Arena &a, int32_t *&rows, double *&G, double *&c, double *&lam, double *&z,
                       double *&u, int32_t *&its, double *&kkt, uint8_t *&flag, int32_t *&tr,
                       int32_t *&ev, double *&GT, double *&CT, double *&GE, double *&CE, double *&sE,
-                      void *&admm_w, void *&est_w, void *&cw) {
-        // draws, counts, distinct rows, weights, sizes, input check flags
-        rows = a.take<int32_t>((size_t)4 * B1 * n + B1 + 4);
+                      void *&admm_w, void *&est_w, void *&cw, int32_t *&gidx, uint64_t *&cs, double *&XU,
+                      double *&bc) {
+        // draws, counts, distinct rows, weights, sizes, input check flags, union size
+        rows = a.take<int32_t>((size_t)4 * B1 * n + B1 + 8);
         G = a.take<double>((size_t)B1 * p * p);
         c = a.take<double>((size_t)B1 * p);
         lam = a.take<double>(q);
@@ -278,16 +279,23 @@ static int lasso_fit(int n, int p, const double *X, const double *y, const uoi_o
         admm_w = a.take<char>(admm_work_bytes(P, o->precision, o->solver));
         est_w = a.take<char>(estim_work_bytes(E));
         cw = a.take<char>(complement_work_bytes(n, p, 1));
+        gidx = a.take<int32_t>(p);
+        cs = a.take<uint64_t>((size_t)q * ((p + 63) / 64));
+        XU = a.take<double>((size_t)n * p);
+        bc = a.take<double>(p);
     };
-    int32_t *rows, *its, *tr, *ev;
-    double *G, *c, *lam, *z, *u, *kkt, *GT, *CT, *GE, *CE, *sE;
+    int32_t *rows, *its, *tr, *ev, *gidx;
+    double *G, *c, *lam, *z, *u, *kkt, *GT, *CT, *GE, *CE, *sE, *XU, *bc;
     uint8_t *flag;
+    uint64_t *cs;
     void *admm_w, *est_w, *cw;
-    layout(ar, rows, G, c, lam, z, u, its, kkt, flag, tr, ev, GT, CT, GE, CE, sE, admm_w, est_w, cw);
+    layout(ar, rows, G, c, lam, z, u, its, kkt, flag, tr, ev, GT, CT, GE, CE, sE, admm_w, est_w, cw, gidx, cs,
+           XU, bc);
     Arena A;
     A.cap = ar.off;
     A.base = (char *)pool_get(ar.off);
-    layout(A, rows, G, c, lam, z, u, its, kkt, flag, tr, ev, GT, CT, GE, CE, sE, admm_w, est_w, cw);
+    layout(A, rows, G, c, lam, z, u, its, kkt, flag, tr, ev, GT, CT, GE, CE, sE, admm_w, est_w, cw, gidx, cs,
+           XU, bc);
     check_finite(s, rows + (size_t)4 * B1 * n + B1, {{X, (size_t)n * p, "X"}, {y, (size_t)n, "y"}});
 
     Timer tm(s, timing);
@@ -316,17 +324,32 @@ static int lasso_fit(int n, int p, const double *X, const double *y, const uoi_o
     tm.mark();
     launch_support_and(s, B1, p, R, z, supp_out);
     tm.mark();
-    // model estimation: splits, training / evaluation statistics, refits, union
+    // model estimation: splits, training / evaluation statistics, refits, union.
+    // The refits read statistics of support columns only: when the union U of the
+    // q supports is at most 3/4 of the columns, the products are formed over
+    // X[:, U] and the supports renumbered; beta* is scattered back at the end.
+    const int nu = launch_support_union(s, q, p, supp_out, rows + (size_t)4 * B1 * n + B1 + 4, gidx);
+    const bool compact = nu > 0 && 4 * (int64_t)nu <= 3 * (int64_t)p;
+    const int pE = compact ? nu : p;
+    const double *XE = X;
+    if (compact) {
+        launch_compact_design(s, q, p, nu, supp_out, gidx, cs, n, X, p, XU);
+        XE = XU;
+        E.p = pE;
+        E.supp = cs;
+    }
     launch_split(s, o->seed, TAG_LASSO_SPLIT, B2, n, ntr, flag);
     launch_compact_rows(s, B2, n, flag, ntr, tr, ev);
     // evaluation products directly; training products as their complement in the
     // full-data product (the split partitions the rows), so the larger training
     // side is never gathered
-    launch_gram_f64(s, B2, nev, ev, nullptr, p, X, p, 1, y, 1, GE, CE, sE, 1);
-    launch_train_from_eval(s, B2, n, p, X, p, 1, y, 1, GE, CE, ntr, nev, nullptr, nullptr, GT, CT, cw);
+    launch_gram_f64(s, B2, nev, ev, nullptr, pE, XE, pE, 1, y, 1, GE, CE, sE, 1);
+    launch_train_from_eval(s, B2, n, pE, XE, pE, 1, y, 1, GE, CE, ntr, nev, nullptr, nullptr, GT, CT, cw);
     tm.mark();
     E.GT = GT; E.CT = CT; E.GE = GE; E.CE = CE; E.sE = sE;
-    estimate(s, E, est_w, beta_out, jstar_out, diag ? diag->losses : nullptr, timing ? sm + 6 : nullptr);
+    estimate(s, E, est_w, compact ? bc : beta_out, jstar_out, diag ? diag->losses : nullptr,
+             timing ? sm + 6 : nullptr);
+    if (compact) launch_scatter_cols(s, p, nu, gidx, bc, beta_out);
     tm.mark();
     if (diag && diag->sel_beta) transpose(s, B1, p, R, z, diag->sel_beta, true);
     UOI_HIP(hipStreamSynchronize(s));

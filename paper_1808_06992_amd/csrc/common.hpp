@@ -267,6 +267,14 @@ void launch_cnorm(hipStream_t s, int nb, int p, int pe, const double *C, double 
 
 // supports: AND over bootstraps of (z != 0);  supp[r][W]
 void launch_support_and(hipStream_t s, int nb, int p, int R, const double *z, uint64_t *supp);
+// union of the R supports: writes its columns to gidx (increasing) and returns
+// their number (synchronises); -1 when p > 65536
+int launch_support_union(hipStream_t s, int R, int p, const uint64_t *supp, int *count, int32_t *gidx);
+// supports in the union's numbering (cs[R][ceil(cnt/64)]) and XU = X[:, gidx]
+void launch_compact_design(hipStream_t s, int R, int p, int cnt, const uint64_t *supp, const int32_t *gidx,
+                           uint64_t *cs, int n, const double *X, int ldx, double *XU);
+// dst[0..p) = 0, dst[gidx[c]] = src[c]
+void launch_scatter_cols(hipStream_t s, int p, int cnt, const int32_t *gidx, const double *src, double *dst);
 
 // estimation
 struct EstimProblem {

@@ -350,11 +350,17 @@ SliceShape slice_shape(int n, int p, int pe) {
 }
 }  // namespace
 
+// enough for any design width up to p (a caller may run on a column subset)
 size_t complement_work_bytes(int n, int p, int pe) {
-    const SliceShape sh = slice_shape(n, p, pe);
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    return al(sizeof(int32_t) * (size_t)sh.ns * sh.mp) + al(sizeof(int32_t) * sh.ns) +
-           al(sizeof(double) * (size_t)sh.ns * p * (p + pe)) + al(sizeof(double) * (size_t)p * (p + pe));
+    size_t most = 0;
+    for (int pp = 1; pp <= p; ++pp) {
+        const SliceShape sh = slice_shape(n, pp, pe);
+        most = std::max(most, al(sizeof(int32_t) * (size_t)sh.ns * sh.mp) + al(sizeof(int32_t) * sh.ns) +
+                                  al(sizeof(double) * (size_t)sh.ns * pp * (pp + pe)) +
+                                  al(sizeof(double) * (size_t)pp * (pp + pe)));
+    }
+    return most;
 }
 
 void launch_train_from_eval(hipStream_t s, int nb, int n, int p, const double *X, int ldx, int pe,

@@ -134,6 +134,34 @@ def test_uoi_lasso_all_refit_paths(api, orc):
             assert np.abs(b - ref["beta"]).max() <= 1e-6 * np.abs(ref["beta"]).max()
 
 
+def test_uoi_lasso_refits_on_support_union(api, orc):
+    """Sparse supports: the union of the q supports covers at most 3/4 of the
+    columns, so the estimation products are formed over those columns only and
+    beta* is scattered back; everything is compared with the oracle's full-width
+    refits."""
+    pr = synth.lasso_random(400, 200, 40, 9, noise=0.5, q=8, B1=6, B2=6, ratio=0.01)
+    seed = 2
+    ref = orc.uoi_lasso(pr.X, pr.y, pr.lambdas, pr.B1, pr.B2, seed, keep_selection=True)
+    assert ref["status"] == 0
+    out = api.lasso_fit(cuda(pr.X), cuda(pr.y), pr.lambdas, pr.B1, pr.B2, seed, kkt_tol=1e-10)
+    assert out["status"] == 0
+    p = pr.X.shape[1]
+    got = words_to_bool(out["supports"].cpu().numpy(), p)
+    want = words_to_bool(ref["supports"], p)
+    union = got.any(0)
+    assert 0 < union.sum() <= 3 * p // 4
+    dec = lasso_decided(orc, pr, seed, ref["sel_beta"])
+    assert np.array_equal(got[dec], want[dec])
+    b = out["beta"].cpu().numpy()
+    assert not np.any(b[~union])
+    if np.array_equal(got, want):
+        np.testing.assert_allclose(out["losses"].cpu().numpy(), ref["losses"], rtol=1e-9)
+        jg = out["jstar"].cpu().numpy()
+        check_jstar(ref["losses"], ref["jstar"], jg)
+        if np.array_equal(jg, ref["jstar"]):
+            assert np.abs(b - ref["beta"]).max() <= 1e-9 * np.abs(ref["beta"]).max()
+
+
 def test_uoi_var_small(api, orc):
     pr = synth.var1(12, 600, 0.15, 0.8, 4, burn=50, q=6, B1=4, B2=4)
     seed = 3
