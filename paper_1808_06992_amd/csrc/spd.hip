@@ -16,8 +16,8 @@
 // and keeps the old panel A_:K, both stored pivot-index-major; (3) an MFMA kernel
 // applies the rank-64 update to the 64x64 tiles on and below the diagonal (the
 // sweep keeps A symmetric).  The first step reads G and adds rho on the
-// diagonal, so no shifted copy is made; a final pass negates and fills the upper
-// triangle.
+// diagonal, so no shifted copy is made; the last step stores the negated result
+// in both triangles.
 #include "common.hpp"
 
 namespace uoi {
@@ -245,7 +245,7 @@ __global__ __launch_bounds__(256) void k_update(int p, int k0, int kb, const dou
                                                 const double *__restrict__ Wt,
                                                 const double *__restrict__ Ot,
                                                 const double *__restrict__ Q,
-                                                double *__restrict__ Qnext) {
+                                                double *__restrict__ Qnext, float *__restrict__ M32) {
     // Workgroup -> (matrix, tile).  When another pivot block follows, the first nb
     // workgroups (dispatched first) take the diagonal tile of that block, one per
     // matrix, and invert it once stored, while the other tiles are updated.  The
@@ -317,6 +317,12 @@ __global__ __launch_bounds__(256) void k_update(int p, int k0, int kb, const dou
     double *Db = dst + (size_t)b * p * p;
     const double *Qb = Q + (size_t)b * NB * NB;
     const bool plain = ti != kt && tj != kt;
+    // After the last block step the values are final: M = -(swept matrix) is
+    // stored in both triangles (the upper one as the exact mirror of the lower one,
+    // transposed through LDS so that its stores are coalesced), with its float32
+    // copy when M32 is given.
+    extern __shared__ double tr[];  // [64][65], last step only
+    float *Fb = M32 ? M32 + (size_t)b * p * p : nullptr;
 #pragma unroll
     for (int fm = 0; fm < 2; ++fm)
 #pragma unroll
@@ -332,46 +338,34 @@ __global__ __launch_bounds__(256) void k_update(int p, int k0, int kb, const dou
                     else if (jK) v = Wb[(size_t)(j - k0) * p + i];          // A_iK Q
                     else if (iK) v = Wb[(size_t)(i - k0) * p + j];          // Q A_Kj = (A_jK Q)'
                 }
-                Db[(size_t)i * p + j] = v;
+                if (next) {
+                    Db[(size_t)i * p + j] = v;
+                } else {
+                    tr[(i - ti * 64) * 65 + (j - tj * 64)] = -v;
+                    if (ti > tj || j <= i) {
+                        Db[(size_t)i * p + j] = -v;
+                        if (Fb) Fb[(size_t)i * p + j] = (float)-v;
+                    }
+                }
             }
+    if (!next) {
+        __syncthreads();
+        // mirror: (r, c) of the transposed tile = (c, r) of this one; on a diagonal
+        // tile only the strict upper part
+        for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+            const int r = e >> 6, c = e & 63;
+            const int gi = tj * 64 + r, gj = ti * 64 + c;
+            if (gi < p && gj < p && (ti > tj || gi < gj)) {
+                const double v = tr[c * 65 + r];
+                Db[(size_t)gi * p + gj] = v;
+                if (Fb) Fb[(size_t)gi * p + gj] = (float)v;
+            }
+        }
+        return;
+    }
     if (pivot) {
         __syncthreads();  // the tile's stores are visible to the whole workgroup
         pivot_block(p, k0 + NB, min(NB, p - k0 - NB), Db, 0.0, Qnext + (size_t)b * NB * NB);
-    }
-}
-
-// (4) M = -(swept matrix), with the upper triangle filled from the lower one:
-// 32x32 tiles on or below the diagonal are read through LDS and written to
-// both positions (diagonal tiles from their lower triangle only).  When M32 is
-// given, the float32 copy of M is written in the same pass.
-__global__ void k_symneg(int p, double *__restrict__ M, float *__restrict__ M32) {
-    __shared__ double t[32][33];
-    const int b = blockIdx.z;
-    const int bi = blockIdx.y, bj = blockIdx.x;
-    if (bj > bi) return;
-    double *Mb = M + (size_t)b * p * p;
-    float *Fb = M32 ? M32 + (size_t)b * p * p : nullptr;
-    const int tx = threadIdx.x, ty = threadIdx.y;
-    double v[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {  // clamped loads, all in flight together
-        const int i = min(bi * 32 + ty + 8 * q, p - 1), j = min(bj * 32 + tx, p - 1);
-        v[q] = Mb[(size_t)i * p + j];
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) t[ty + 8 * q][tx] = v[q];
-    __syncthreads();
-    for (int r = ty; r < 32; r += 8) {
-        const int i = bi * 32 + r, j = bj * 32 + tx;      // lower position
-        if (i < p && j < p && (bi > bj || r >= tx)) {
-            Mb[(size_t)i * p + j] = -t[r][tx];
-            if (Fb) Fb[(size_t)i * p + j] = (float)-t[r][tx];
-        }
-        const int i2 = bj * 32 + r, j2 = bi * 32 + tx;    // upper position (i2, j2) = (j, i)
-        if (i2 < p && j2 < p && (bi > bj || tx > r)) {
-            Mb[(size_t)i2 * p + j2] = -t[tx][r];
-            if (Fb) Fb[(size_t)i2 * p + j2] = (float)-t[tx][r];
-        }
     }
 }
 
@@ -411,13 +405,13 @@ void spd_inverse_f64(hipStream_t s, int nb, int p, const double *G, double rho, 
         const double sh = k0 == 0 ? rho : 0.0;
         double *Q = Qbuf[K & 1];
         hipLaunchKernelGGL(k_panel, dim3(T, nb), dim3(256), 0, s, p, k0, kb, src, sh, Q, Wt, Ot);
-        hipLaunchKernelGGL(k_update, dim3(T * (T + 1) / 2, 1, nb), dim3(256), 0, s, p, k0, kb, src, sh, M,
-                           Wt, Ot, Q, Qbuf[(K + 1) & 1]);
+        // the last step also writes the upper triangle and the float32 copy
+        const bool last = k0 + NB >= p;
+        const size_t lds = last ? sizeof(double) * 64 * 65 : 0;
+        hipLaunchKernelGGL(k_update, dim3(T * (T + 1) / 2, 1, nb), dim3(256), lds, s, p, k0, kb, src, sh, M,
+                           Wt, Ot, Q, Qbuf[(K + 1) & 1], last ? M32 : nullptr);
         UOI_LAUNCH_CHECK();
     }
-    const int T32 = (int)cdiv(p, 32);
-    hipLaunchKernelGGL(k_symneg, dim3(T32, T32, nb), dim3(32, 8), 0, s, p, M, M32);
-    UOI_LAUNCH_CHECK();
 }
 
 }  // namespace uoi
