@@ -74,9 +74,14 @@ __device__ double eval_loss(int s, const int *idx, const double *bv, const doubl
                             const double *CEb, int p, int pe, int e, double sE) {
     __shared__ double red[8];
     double part = 0.0;
-    for (int t = threadIdx.x; t < s * s; t += blockDim.x) {
-        int a = t / s, c = t % s;
-        part += bv[a] * GEb[(size_t)idx[a] * p + idx[c]] * bv[c];
+    {   // b' G_E b over the members; thread (ty, tx) of a (blockDim/16) x 16 grid
+        const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15, ny = blockDim.x >> 4;
+        for (int a = ty; a < s; a += ny) {
+            const double *row = GEb + (size_t)idx[a] * p;
+            double ra = 0.0;
+            for (int c = tx; c < s; c += 16) ra += row[idx[c]] * bv[c];
+            part += bv[a] * ra;
+        }
     }
     for (int a = threadIdx.x; a < s; a += blockDim.x) part -= 2.0 * bv[a] * CEb[(size_t)idx[a] * pe + e];
     part = wave_sum(part);
@@ -135,10 +140,12 @@ __global__ __launch_bounds__(256) void k_ols_small(int p, int pe, int R, int W,
         const double dj = Ls[j * s + j];
         for (int i = j + 1 + threadIdx.x; i < s; i += 256) Ls[i * s + j] /= dj;
         __syncthreads();
-        const int n = s - j - 1;
-        for (int t = threadIdx.x; t < n * n; t += 256) {
-            int i = j + 1 + t / n, c = j + 1 + t % n;
-            if (c <= i) Ls[i * s + c] -= Ls[i * s + j] * Ls[c * s + j];
+        {   // trailing update of the lower triangle; thread (ty, tx) of a 16 x 16 grid
+            const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+            for (int i = j + 1 + ty; i < s; i += 16) {
+                const double lij = Ls[i * s + j];
+                for (int c = j + 1 + tx; c <= i; c += 16) Ls[i * s + c] -= lij * Ls[c * s + j];
+            }
         }
         __syncthreads();
     }
