@@ -642,8 +642,11 @@ void estimate(hipStream_t s, const EstimProblem &E, void *work, double *beta_out
             off.clear();
             used = 0;
         };
-        for (int k = 0; k < E.nb; ++k)
-            for (int r : mids) {
+        // largest systems first: the launch lasts as long as its slowest
+        // workgroup, so the long ones must not start in a late round
+        std::stable_sort(mids.begin(), mids.end(), [&](int a, int b) { return hc[a] > hc[b]; });
+        for (int r : mids)
+            for (int k = 0; k < E.nb; ++k) {
                 const size_t need = (size_t)(hc[r] + 1) * hc[r];
                 if (used + need > cap) flush();
                 sys.push_back(make_int2(k, r));
