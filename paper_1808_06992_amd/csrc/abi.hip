@@ -31,6 +31,21 @@ std::map<int, PoolEntry> g_pool;
 std::map<int, PoolEntry> g_pinned;
 }  // namespace
 
+AuxStream &aux_stream() {
+    static std::mutex mu;
+    static std::map<int, AuxStream> m;
+    int dev = 0;
+    UOI_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    AuxStream &a = m[dev];
+    if (!a.s) {
+        UOI_HIP(hipStreamCreateWithFlags(&a.s, hipStreamNonBlocking));
+        UOI_HIP(hipEventCreateWithFlags(&a.e0, hipEventDisableTiming));
+        UOI_HIP(hipEventCreateWithFlags(&a.e1, hipEventDisableTiming));
+    }
+    return a;
+}
+
 int *pinned_ints(size_t n) {
     int dev = 0;
     UOI_HIP(hipGetDevice(&dev));

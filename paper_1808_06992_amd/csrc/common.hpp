@@ -45,6 +45,13 @@ void pool_release();
 // Pinned host ints for asynchronous readbacks of small results (grow-only, one
 // buffer per device, like the pool; calls that overlap on one device race).
 int *pinned_ints(size_t n);
+// A second stream of the current device (default priority, non-blocking) with
+// two events, for independent kernels that can run beside the caller's stream.
+struct AuxStream {
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+};
+AuxStream &aux_stream();
 
 struct Arena {
     char *base = nullptr;

@@ -616,11 +616,16 @@ void estimate(hipStream_t s, const EstimProblem &E, void *work, double *beta_out
         for (auto &e : ev) UOI_HIP(hipEventCreate(&e));
         UOI_HIP(hipEventRecord(ev[0], s));
     }
-    // small supports
+    // small supports, on a second stream beside the mid-size ones (they write
+    // disjoint systems' results; the mid-size launch ends with a few long systems)
+    AuxStream &ax = aux_stream();
+    UOI_HIP(hipEventRecord(ax.e0, s));
+    UOI_HIP(hipStreamWaitEvent(ax.s, ax.e0, 0));
     size_t lds = sizeof(double) * (size_t)smax * smax;
-    hipLaunchKernelGGL(k_ols_small, dim3(E.R, E.nb), dim3(256), lds, s, E.p, E.pe, E.R, W, E.supp,
+    hipLaunchKernelGGL(k_ols_small, dim3(E.R, E.nb), dim3(256), lds, ax.s, E.p, E.pe, E.R, W, E.supp,
                        w.cnt, E.GT, E.CT, E.GE, E.CE, E.sE, w.Fit, w.loss, w.flags);
     UOI_LAUNCH_CHECK();
+    UOI_HIP(hipEventRecord(ax.e1, ax.s));
     // mid-size supports: blocked Cholesky per (split, support), in chunks that fit
     // the factor scratch
     if (!mids.empty()) {
@@ -655,6 +660,7 @@ void estimate(hipStream_t s, const EstimProblem &E, void *work, double *beta_out
             }
         flush();
     }
+    UOI_HIP(hipStreamWaitEvent(s, ax.e1, 0));
     // large supports by batched conjugate gradients
     if (nL) {
         size_t ns = (size_t)E.nb * nL;
