@@ -330,19 +330,24 @@ __global__ __launch_bounds__(256) void k_cnorm(int p, int pe, const double *__re
 constexpr double kStallRatio = 0.7;
 constexpr double kParkFactor = 3.0;
 constexpr double kStallFactor = 30.0;
-__global__ void k_freeze(int nb, int R, int pe, const double *__restrict__ vmax,
+__global__ void k_freeze(int nb, int R, int pe, double *__restrict__ vmax,
                          const double *__restrict__ cn, double tol, double park_tol,
                          double stall_tol, int it, uint8_t *__restrict__ state,
                          int32_t *__restrict__ iters, double *__restrict__ kkt,
-                         int *__restrict__ active) {
-    // active[0] = all solves still active, active[1 + b] = those of bootstrap b
+                         int *__restrict__ active, int *__restrict__ active_next) {
+    // active[0] = all solves still active, active[1 + b] = those of bootstrap b;
+    // the next check's counters and maxima are cleared here, so that no fill
+    // kernel is needed between checks
     int s = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int i = s; i < 1 + nb; i += gridDim.x * blockDim.x) active_next[i] = 0;
     bool act = false;
     if (s < nb * R) {
         int b = s / R, r = s % R;
+        const double vm = vmax[s];
+        vmax[s] = 0.0;
         if (state[s] == 0) {
             double c = cn[(size_t)b * pe + r % pe];
-            double rel = c > 0.0 ? vmax[s] / c : vmax[s];
+            double rel = c > 0.0 ? vm / c : vm;
             const double prev = kkt[s];
             kkt[s] = rel;
             if (rel <= tol) {
@@ -657,7 +662,7 @@ AdmmWork carve(const AdmmProblem &P, int precision, int solver, Arena &ar) {
     w.cn = ar.take<double>((size_t)P.nb * P.pe);
     w.vmax = ar.take<double>((size_t)P.nb * P.R);
     w.state = ar.take<uint8_t>((size_t)P.nb * P.R);
-    w.active = ar.take<int>(1 + P.nb);
+    w.active = ar.take<int>(2 * (1 + P.nb));  // two sets of counters, alternating per check
     w.stat = ar.take<int>(2);
     if (solver == UOI_SOLVER_BATCHED) {
         w.v0 = ar.take<double>(nst);
@@ -684,13 +689,14 @@ size_t admm_work_bytes(const AdmmProblem &P, int precision, int solver) {
 
 // KKT evaluation of (a subset of) solves followed by the freeze step, and an
 // asynchronous copy of the active counts ([0] all, [1 + b] per bootstrap) into
-// pinned host memory, marked by an event.
+// pinned host memory, marked by an event.  The maxima and the counters of
+// buffer `parity` are zero on entry (cleared by the previous check's freeze, or
+// at the start of the sweep); this check clears the other buffer.
 template <typename T>
 static void check_launch(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T *z,
                          bool only_active, double park_tol, double stall_tol, int it, AdmmOut &out,
-                         int *hact, hipEvent_t ev) {
-    UOI_HIP(hipMemsetAsync(w.vmax, 0, sizeof(double) * (size_t)P.nb * P.R, s));
-    UOI_HIP(hipMemsetAsync(w.active, 0, sizeof(int) * (1 + P.nb), s));
+                         int *hact, hipEvent_t ev, int parity) {
+    int *act = w.active + (size_t)parity * (1 + P.nb), *act_next = w.active + (size_t)(parity ^ 1) * (1 + P.nb);
     if (std::is_same<T, double>::value) {
         UOI_DISPATCH_FN(P.R, {
             KktEpi<double, 1, FN> epi{P.C, (const double *)z, w.state, P.lam, w.vmax, P.p, P.R, P.pe,
@@ -710,9 +716,9 @@ static void check_launch(hipStream_t s, const AdmmProblem &P, const AdmmWork &w,
     }
     int ns = P.nb * P.R;
     hipLaunchKernelGGL(k_freeze, dim3(cdiv(ns, 256)), dim3(256), 0, s, P.nb, P.R, P.pe, w.vmax, w.cn,
-                       P.tol, park_tol, stall_tol, it, w.state, out.iters, out.kkt, w.active);
+                       P.tol, park_tol, stall_tol, it, w.state, out.iters, out.kkt, act, act_next);
     UOI_LAUNCH_CHECK();
-    UOI_HIP(hipMemcpyAsync(hact, w.active, sizeof(int) * (1 + P.nb), hipMemcpyDeviceToHost, s));
+    UOI_HIP(hipMemcpyAsync(hact, act, sizeof(int) * (1 + P.nb), hipMemcpyDeviceToHost, s));
     UOI_HIP(hipEventRecord(ev, s));
 }
 
@@ -785,14 +791,20 @@ static int sweep(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T
         pc.flops = fl * pc.n;
         pc.used = true;
     };
-    check_launch<T>(s, P, w, z, true, park_tol, stall_tol, it, out, hact, ev);
+    // cleared once here; each check clears the next one's buffers
+    UOI_HIP(hipMemsetAsync(w.vmax, 0, sizeof(double) * (size_t)P.nb * P.R, s));
+    UOI_HIP(hipMemsetAsync(w.active, 0, sizeof(int) * 2 * (1 + P.nb), s));
+    int parity = 0;
+    check_launch<T>(s, P, w, z, true, park_tol, stall_tol, it, out, hact, ev, parity);
+    parity ^= 1;
     int active = check_wait(ev, hact, P.nb, act_b);
     if (active > 0 && it < it_cap) {
         run_chunk(std::min(P.check_every, it_cap - it));
         account(pend.back());
         it = itq;
         for (;;) {
-            check_launch<T>(s, P, w, z, true, park_tol, stall_tol, it, out, hact, ev);
+            check_launch<T>(s, P, w, z, true, park_tol, stall_tol, it, out, hact, ev, parity);
+            parity ^= 1;
             const bool spec = it < it_cap;
             if (spec) run_chunk(std::min(P.check_every, it_cap - it));
             active = check_wait(ev, hact, P.nb, act_b);
