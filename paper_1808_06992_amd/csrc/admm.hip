@@ -15,7 +15,9 @@
 // Convergence is the relative KKT residual of the LASSO (evaluated in float64
 // with the float64 Gram) every `check_every` iterations; a solve that meets the
 // tolerance is frozen (its z is the verified iterate) and a tile whose solves
-// are all frozen skips its work.
+// are all frozen skips its work.  The float32 phase of the mixed path parks
+// solves on a KKT estimate that its iteration yields without a product; every
+// parked solve is then verified (and finished if needed) in float64.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -119,6 +121,15 @@ struct AdmmEpi {
 // written as the three bfloat16 planes Vp[b][part][r][i] (parts as in
 // split_bf16x3; rows i >= p are never written and stay zero).  A lane holds four
 // consecutive rows i of one column r, so each part is one 8-byte store.
+//
+// With vmax set (the last iteration before a check), the iteration also leaves
+// a KKT estimate per solve without a product by G: the x-update solves
+// (G + rho I) x = c + rho (z - u), so the gradient at x is
+//     c - G x = rho (x - z + u)          (z, u before the update)
+// and the KKT violation is evaluated with that gradient at the new z (its
+// support and signs).  It differs from the one at z by G (x - z), which
+// vanishes as the iteration converges; the float32 phase uses it only to park
+// solves, and the float64 phase decides convergence with the exact residual.
 template <int FN>
 struct AdmmEpiBf3 {
     const float *h;      // [nb][p][pe]
@@ -128,6 +139,7 @@ struct AdmmEpiBf3 {
     const double *lam;
     int p, R, pe, ldk;
     float rho, inv_rho, alpha;
+    double *vmax;        // [nb][R] per-solve maximum (atomic), or null
     __device__ bool tile_active(int b, int r0, int w) const {
         const int lane = threadIdx.x & 63, r = r0 + lane;
         const bool a = lane < w && r < R && state[(size_t)b * R + min(r, R - 1)] == 0;
@@ -154,7 +166,7 @@ struct AdmmEpiBf3 {
             for (int c = 0; c < FN; ++c) {
                 const size_t o = ((size_t)b * p + ic) * R + rc[c];
                 uv[c][t] = u[o];
-                zv[c][t] = relaxed ? z[o] : 0.0f;
+                zv[c][t] = relaxed || vmax ? z[o] : 0.0f;
                 hv[c][t] = h[((size_t)b * p + ic) * pe + rc[c] % pe];
             }
         }
@@ -163,12 +175,13 @@ struct AdmmEpiBf3 {
         for (int c = 0; c < FN; ++c) {
             if (!act[c]) continue;
             const int r = r0 + 16 * c + lr;
-            float vv[4];
+            float vv[4], kv = 0.0f;
+            const float lamf = thr[c] * rho;
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const int i = i4 + t;
-                float x = hv[c][t] + rho * acc[0][c][t];
-                if (relaxed) x = alpha * x + (1.0f - alpha) * zv[c][t];
+                const float x0 = hv[c][t] + rho * acc[0][c][t];
+                const float x = relaxed ? alpha * x0 + (1.0f - alpha) * zv[c][t] : x0;
                 const float uo = uv[c][t];
                 const float zn = soft_threshold(x + uo, thr[c]);
                 const float un = uo + x - zn;
@@ -177,7 +190,19 @@ struct AdmmEpiBf3 {
                     const size_t o = ((size_t)b * p + i) * R + r;
                     z[o] = zn;
                     u[o] = un;
+                    if (vmax) {
+                        const float g = rho * (x0 - zv[c][t] + uo);
+                        const float v = zn != 0.0f ? fabsf(g - (zn > 0.0f ? lamf : -lamf))
+                                                   : fmaxf(0.0f, fabsf(g) - lamf);
+                        kv = fmaxf(kv, v);
+                    }
                 }
+            }
+            if (vmax) {
+                // lanes lr, lr+16, lr+32, lr+48 hold the same solve
+                kv = fmaxf(kv, __shfl_xor(kv, 16));
+                kv = fmaxf(kv, __shfl_xor(kv, 32));
+                if (lk == 0 && kv > 0.0f) atomic_max_nonneg(&vmax[(size_t)b * R + r], (double)kv);
             }
             __bf16 *dst = vp + (size_t)b * 3 * plane + (size_t)r * ldk + i4;
             if (i4 + 3 < p) {
@@ -326,9 +351,10 @@ __global__ __launch_bounds__(256) void k_cnorm(int p, int pe, const double *__re
 // parked when it meets park_tol, or when it is within stall_tol but its KKT
 // residual fell by less than kStallRatio since the previous check (it has
 // reached what float32 arithmetic resolves).  kkt[] holds the previous value
-// (initialised to a huge number).
+// (initialised to a huge number).  iters[] is -1 while a solve is active, -(it+2)
+// while it is parked at iteration it, and its iteration count once converged.
 constexpr double kStallRatio = 0.7;
-constexpr double kParkFactor = 3.0;
+constexpr double kParkFactor = 5.0;
 constexpr double kStallFactor = 30.0;
 __global__ void k_freeze(int nb, int R, int pe, double *__restrict__ vmax,
                          const double *__restrict__ cn, double tol, double park_tol,
@@ -350,13 +376,18 @@ __global__ void k_freeze(int nb, int R, int pe, double *__restrict__ vmax,
             double rel = c > 0.0 ? vm / c : vm;
             const double prev = kkt[s];
             kkt[s] = rel;
+            const int32_t ip = iters[s];
             if (rel <= tol) {
+                // a parked solve that meets the tolerance without further
+                // iterations keeps the iteration at which it was parked
                 state[s] = 1;
-                iters[s] = it;
+                iters[s] = ip <= -2 ? -ip - 2 : it;
             } else if (rel <= park_tol || (rel <= stall_tol && rel > kStallRatio * prev)) {
                 state[s] = 2;
+                if (ip == -1) iters[s] = -it - 2;  // provisional, still counted as unconverged
             } else {
                 act = true;
+                if (ip <= -2) iters[s] = -1;
                 atomicAdd(&active[1 + b], 1);
             }
         }
@@ -692,12 +723,16 @@ size_t admm_work_bytes(const AdmmProblem &P, int precision, int solver) {
 // pinned host memory, marked by an event.  The maxima and the counters of
 // buffer `parity` are zero on entry (cleared by the previous check's freeze, or
 // at the start of the sweep); this check clears the other buffer.
+// With `estimate`, the maxima were left by the last iteration's epilogue (the
+// float32 KKT estimate): no product is run, and a solve that meets the
+// tolerance is parked rather than converged.
 template <typename T>
 static void check_launch(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T *z,
                          bool only_active, double park_tol, double stall_tol, int it, AdmmOut &out,
-                         int *hact, hipEvent_t ev, int parity) {
+                         int *hact, hipEvent_t ev, int parity, bool estimate) {
     int *act = w.active + (size_t)parity * (1 + P.nb), *act_next = w.active + (size_t)(parity ^ 1) * (1 + P.nb);
-    if (std::is_same<T, double>::value) {
+    if (estimate) {
+    } else if (std::is_same<T, double>::value) {
         UOI_DISPATCH_FN(P.R, {
             KktEpi<double, 1, FN> epi{P.C, (const double *)z, w.state, P.lam, w.vmax, P.p, P.R, P.pe,
                                       only_active};
@@ -716,7 +751,8 @@ static void check_launch(hipStream_t s, const AdmmProblem &P, const AdmmWork &w,
     }
     int ns = P.nb * P.R;
     hipLaunchKernelGGL(k_freeze, dim3(cdiv(ns, 256)), dim3(256), 0, s, P.nb, P.R, P.pe, w.vmax, w.cn,
-                       P.tol, park_tol, stall_tol, it, w.state, out.iters, out.kkt, act, act_next);
+                       estimate ? -1.0 : P.tol, park_tol, stall_tol, it, w.state, out.iters, out.kkt, act,
+                       act_next);
     UOI_LAUNCH_CHECK();
     UOI_HIP(hipMemcpyAsync(hact, act, sizeof(int) * (1 + P.nb), hipMemcpyDeviceToHost, s));
     UOI_HIP(hipEventRecord(ev, s));
@@ -766,7 +802,8 @@ static int sweep(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T
                     __bf16 *pin = (itq & 1) ? w.vp1 : w.vp0;
                     __bf16 *pout = (itq & 1) ? w.vp0 : w.vp1;
                     AdmmEpiBf3<FN> epi{h, z, u, pout, w.state, P.lam, P.p, P.R, P.pe, bf3_ldk(P.p),
-                                       (float)P.rho, (float)(1.0 / P.rho), (float)P.relax};
+                                       (float)P.rho, (float)(1.0 / P.rho), (float)P.relax,
+                                       t == n - 1 ? w.vmax : nullptr};
                     run_bgemm_bf3<FN>(s, P.nb, P.p, P.R, M, pin, epi);
                 } else {
                     AdmmEpi<T, 1, FN> epi{h, z, u, vout, w.state, P.lam, P.p, P.R, P.pe, (T)P.rho,
@@ -795,7 +832,10 @@ static int sweep(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T
     UOI_HIP(hipMemsetAsync(w.vmax, 0, sizeof(double) * (size_t)P.nb * P.R, s));
     UOI_HIP(hipMemsetAsync(w.active, 0, sizeof(int) * 2 * (1 + P.nb), s));
     int parity = 0;
-    check_launch<T>(s, P, w, z, true, park_tol, stall_tol, it, out, hact, ev, parity);
+    // the first check evaluates the exact residual; the later ones of the float32
+    // sweep take the estimate left by the chunk's last iteration
+    constexpr bool kEstimate = std::is_same<T, float>::value;
+    check_launch<T>(s, P, w, z, true, park_tol, stall_tol, it, out, hact, ev, parity, false);
     parity ^= 1;
     int active = check_wait(ev, hact, P.nb, act_b);
     if (active > 0 && it < it_cap) {
@@ -803,7 +843,7 @@ static int sweep(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T
         account(pend.back());
         it = itq;
         for (;;) {
-            check_launch<T>(s, P, w, z, true, park_tol, stall_tol, it, out, hact, ev, parity);
+            check_launch<T>(s, P, w, z, true, park_tol, stall_tol, it, out, hact, ev, parity, kEstimate);
             parity ^= 1;
             const bool spec = it < it_cap;
             if (spec) run_chunk(std::min(P.check_every, it_cap - it));
@@ -938,9 +978,10 @@ void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, 
         active = sweep<double>(s, P, w, w.M, w.h, out.z, out.u, w.v0, w.v1, it, P.max_iter, P.tol, 0.0,
                                out);
     } else {
-        // float32 phase: operator and state in float32, KKT in float64; solves that
-        // reach kParkFactor x the tolerance, or stall within kStallFactor x the
-        // tolerance, are parked and finished in float64.
+        // float32 phase: operator and state in float32, first KKT check in
+        // float64, later ones on the iteration's estimate; solves whose estimate
+        // reaches kParkFactor x the tolerance, or stalls within kStallFactor x
+        // the tolerance, are parked, then verified and finished in float64.
         // (the float32 copy of M was written by the factorization)
         size_t nh = (size_t)P.nb * P.p * P.pe;
         hipLaunchKernelGGL(k_f64_to_f32, dim3(cdiv(nh, 256)), dim3(256), 0, s, nh, w.h, w.h32);

@@ -101,6 +101,27 @@ def test_spd_inverse_parity(api, orc, p, nb):
             assert np.array_equal(M[b], M[b].T)
 
 
+@pytest.mark.parametrize("p,nb", [(1000, 7), (700, 48)])
+def test_spd_inverse_parity_many_tiles(api, p, nb):
+    """More tiles per block step than workgroups resident at once, so most tiles
+    are taken from the update's per-XCD queues; odd batch and a ragged last block
+    (p = 700)."""
+    rng = np.random.default_rng(p + nb)
+    n = 2 * p
+    G = np.empty((nb, p, p))
+    for b in range(nb):
+        X = rng.standard_normal((n, p))
+        G[b] = X.T @ X / n
+    M = api.spd_inverse(cuda(G), 1.0).cpu().numpy()
+    for b in sorted({0, nb // 2, nb - 1}):
+        ref = np.linalg.inv(G[b] + np.eye(p))
+        np.testing.assert_allclose(M[b], ref, rtol=1e-11, atol=1e-13 * np.abs(ref).max())
+        assert np.array_equal(M[b], M[b].T)
+    # every matrix: residual of (G + I) M = I
+    R = np.einsum("bij,bjk->bik", G + np.eye(p), M) - np.eye(p)
+    assert np.abs(R).max() < 1e-11
+
+
 # --------------------------------------------------------------------------- ADMM
 
 def _oracle_solutions(orc, G, c, lams):
