@@ -127,9 +127,13 @@ struct AdmmEpi {
 // (G + rho I) x = c + rho (z - u), so the gradient at x is
 //     c - G x = rho (x - z + u)          (z, u before the update)
 // and the KKT violation is evaluated with that gradient at the new z (its
-// support and signs).  It differs from the one at z by G (x - z), which
-// vanishes as the iteration converges; the float32 phase uses it only to park
-// solves, and the float64 phase decides convergence with the exact residual.
+// support and signs).  Each entry of the violation is 1-Lipschitz in the
+// gradient, and the gradient at z differs from the one at x by G (x - z), so
+//     KKT(z) <= max_j v_j + ||G||_inf ||x - z||_inf.
+// The epilogue leaves the two maxima per solve (vmax, rmax) and the freeze step
+// combines them with ||G||_inf of the bootstrap (weighted, kResidualWeight).
+// The float32 phase uses the estimate only to park solves; the float64 phase
+// decides convergence with the exact residual.
 template <int FN>
 struct AdmmEpiBf3 {
     const float *h;      // [nb][p][pe]
@@ -139,7 +143,8 @@ struct AdmmEpiBf3 {
     const double *lam;
     int p, R, pe, ldk;
     float rho, inv_rho, alpha;
-    double *vmax;        // [nb][R] per-solve maximum (atomic), or null
+    double *vmax;        // [nb][R] per-solve maximum of v (atomic), or null
+    double *rmax;        // [nb][R] per-solve maximum of |x - z| (atomic)
     __device__ bool tile_active(int b, int r0, int w) const {
         const int lane = threadIdx.x & 63, r = r0 + lane;
         const bool a = lane < w && r < R && state[(size_t)b * R + min(r, R - 1)] == 0;
@@ -175,7 +180,7 @@ struct AdmmEpiBf3 {
         for (int c = 0; c < FN; ++c) {
             if (!act[c]) continue;
             const int r = r0 + 16 * c + lr;
-            float vv[4], kv = 0.0f;
+            float vv[4], kv = 0.0f, rv = 0.0f;
             const float lamf = thr[c] * rho;
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
@@ -195,6 +200,7 @@ struct AdmmEpiBf3 {
                         const float v = zn != 0.0f ? fabsf(g - (zn > 0.0f ? lamf : -lamf))
                                                    : fmaxf(0.0f, fabsf(g) - lamf);
                         kv = fmaxf(kv, v);
+                        rv = fmaxf(rv, fabsf(x0 - zn));
                     }
                 }
             }
@@ -202,7 +208,10 @@ struct AdmmEpiBf3 {
                 // lanes lr, lr+16, lr+32, lr+48 hold the same solve
                 kv = fmaxf(kv, __shfl_xor(kv, 16));
                 kv = fmaxf(kv, __shfl_xor(kv, 32));
+                rv = fmaxf(rv, __shfl_xor(rv, 16));
+                rv = fmaxf(rv, __shfl_xor(rv, 32));
                 if (lk == 0 && kv > 0.0f) atomic_max_nonneg(&vmax[(size_t)b * R + r], (double)kv);
+                if (lk == 0 && rv > 0.0f) atomic_max_nonneg(&rmax[(size_t)b * R + r], (double)rv);
             }
             __bf16 *dst = vp + (size_t)b * 3 * plane + (size_t)r * ldk + i4;
             if (i4 + 3 < p) {
@@ -356,8 +365,16 @@ __global__ __launch_bounds__(256) void k_cnorm(int p, int pe, const double *__re
 constexpr double kStallRatio = 0.7;
 constexpr double kParkFactor = 5.0;
 constexpr double kStallFactor = 30.0;
-__global__ void k_freeze(int nb, int R, int pe, double *__restrict__ vmax,
-                         const double *__restrict__ cn, double tol, double park_tol,
+// Weight of ||G||_inf ||x - z||_inf in the float32 KKT estimate.  1 gives a
+// strict bound, which float32 rounding of x - z keeps above the parking
+// threshold for some solves; G (x - z) is far below that worst case in
+// practice.  Over 0.05 - 0.3 the LASSO fit was fastest at 0.05 - 0.1 and the
+// slowly converging VAR fit at 0.2 - 0.3; without the term (0) the VAR fit
+// parks too early and was 40 % slower.
+constexpr double kResidualWeight = 0.1;
+__global__ void k_freeze(int nb, int R, int pe, double *__restrict__ vmax, double *__restrict__ rmax,
+                         const double *__restrict__ gn, const double *__restrict__ cn, double tol,
+                         double park_tol,
                          double stall_tol, int it, uint8_t *__restrict__ state,
                          int32_t *__restrict__ iters, double *__restrict__ kkt,
                          int *__restrict__ active, int *__restrict__ active_next) {
@@ -369,8 +386,11 @@ __global__ void k_freeze(int nb, int R, int pe, double *__restrict__ vmax,
     bool act = false;
     if (s < nb * R) {
         int b = s / R, r = s % R;
-        const double vm = vmax[s];
+        // an estimate with its residual term (rmax is zero after an exact
+        // evaluation)
+        const double vm = vmax[s] + (gn ? kResidualWeight * gn[b] * rmax[s] : 0.0);
         vmax[s] = 0.0;
+        rmax[s] = 0.0;
         if (state[s] == 0) {
             double c = cn[(size_t)b * pe + r % pe];
             double rel = c > 0.0 ? vm / c : vm;
@@ -671,9 +691,37 @@ void launch_cnorm(hipStream_t s, int nb, int p, int pe, const double *C, double 
     UOI_LAUNCH_CHECK();
 }
 
+// gn[b] = ||G_b||_inf = max_j sum_i |G_b[i][j]| (G symmetric: the largest
+// absolute column sum).  Block: 64 columns x 4 row groups; the per-block maximum
+// goes to gn[b] by an atomic maximum (gn zeroed before).
+__global__ __launch_bounds__(256) void k_gnorm(int p, const double *__restrict__ G,
+                                               double *__restrict__ gn) {
+    __shared__ double red[4][64];
+    const int b = blockIdx.y;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + tx, jc = min(j, p - 1);
+    const double *Gb = G + (size_t)b * p * p;
+    double sum = 0.0;
+    for (int i0 = ty; i0 < p; i0 += 32) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = Gb[(size_t)min(i0 + 4 * u, p - 1) * p + jc];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (i0 + 4 * u < p) sum += fabs(v[u]);
+    }
+    red[ty][tx] = sum;
+    __syncthreads();
+    if (ty == 0) {
+        double m = j < p ? red[0][tx] + red[1][tx] + red[2][tx] + red[3][tx] : 0.0;
+        m = wave_max(m);
+        if (tx == 0) atomic_max_nonneg(&gn[b], m);
+    }
+}
+
 namespace {
 struct AdmmWork {
-    double *M, *h, *cn, *vmax;
+    double *M, *h, *cn, *vmax, *rmax, *gn;
     uint8_t *state;
     int *active;
     int *stat;  // [0] unconverged solves, [1] largest iteration count
@@ -692,6 +740,8 @@ AdmmWork carve(const AdmmProblem &P, int precision, int solver, Arena &ar) {
     w.h = ar.take<double>((size_t)P.nb * P.p * P.pe);
     w.cn = ar.take<double>((size_t)P.nb * P.pe);
     w.vmax = ar.take<double>((size_t)P.nb * P.R);
+    w.rmax = ar.take<double>((size_t)P.nb * P.R);
+    w.gn = ar.take<double>(P.nb);
     w.state = ar.take<uint8_t>((size_t)P.nb * P.R);
     w.active = ar.take<int>(2 * (1 + P.nb));  // two sets of counters, alternating per check
     w.stat = ar.take<int>(2);
@@ -750,9 +800,9 @@ static void check_launch(hipStream_t s, const AdmmProblem &P, const AdmmWork &w,
         });
     }
     int ns = P.nb * P.R;
-    hipLaunchKernelGGL(k_freeze, dim3(cdiv(ns, 256)), dim3(256), 0, s, P.nb, P.R, P.pe, w.vmax, w.cn,
-                       estimate ? -1.0 : P.tol, park_tol, stall_tol, it, w.state, out.iters, out.kkt, act,
-                       act_next);
+    hipLaunchKernelGGL(k_freeze, dim3(cdiv(ns, 256)), dim3(256), 0, s, P.nb, P.R, P.pe, w.vmax, w.rmax,
+                       estimate ? (const double *)w.gn : nullptr, w.cn, estimate ? -1.0 : P.tol, park_tol,
+                       stall_tol, it, w.state, out.iters, out.kkt, act, act_next);
     UOI_LAUNCH_CHECK();
     UOI_HIP(hipMemcpyAsync(hact, act, sizeof(int) * (1 + P.nb), hipMemcpyDeviceToHost, s));
     UOI_HIP(hipEventRecord(ev, s));
@@ -803,7 +853,7 @@ static int sweep(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T
                     __bf16 *pout = (itq & 1) ? w.vp0 : w.vp1;
                     AdmmEpiBf3<FN> epi{h, z, u, pout, w.state, P.lam, P.p, P.R, P.pe, bf3_ldk(P.p),
                                        (float)P.rho, (float)(1.0 / P.rho), (float)P.relax,
-                                       t == n - 1 ? w.vmax : nullptr};
+                                       t == n - 1 ? w.vmax : nullptr, w.rmax};
                     run_bgemm_bf3<FN>(s, P.nb, P.p, P.R, M, pin, epi);
                 } else {
                     AdmmEpi<T, 1, FN> epi{h, z, u, vout, w.state, P.lam, P.p, P.R, P.pe, (T)P.rho,
@@ -830,6 +880,7 @@ static int sweep(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T
     };
     // cleared once here; each check clears the next one's buffers
     UOI_HIP(hipMemsetAsync(w.vmax, 0, sizeof(double) * (size_t)P.nb * P.R, s));
+    UOI_HIP(hipMemsetAsync(w.rmax, 0, sizeof(double) * (size_t)P.nb * P.R, s));
     UOI_HIP(hipMemsetAsync(w.active, 0, sizeof(int) * 2 * (1 + P.nb), s));
     int parity = 0;
     // the first check evaluates the exact residual; the later ones of the float32
@@ -983,6 +1034,8 @@ void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, 
         // reaches kParkFactor x the tolerance, or stalls within kStallFactor x
         // the tolerance, are parked, then verified and finished in float64.
         // (the float32 copy of M was written by the factorization)
+        UOI_HIP(hipMemsetAsync(w.gn, 0, sizeof(double) * P.nb, s));
+        hipLaunchKernelGGL(k_gnorm, dim3(cdiv(P.p, 64), P.nb), dim3(256), 0, s, P.p, P.G, w.gn);
         size_t nh = (size_t)P.nb * P.p * P.pe;
         hipLaunchKernelGGL(k_f64_to_f32, dim3(cdiv(nh, 256)), dim3(256), 0, s, nh, w.h, w.h32);
         hipLaunchKernelGGL(k_f64_to_f32, dim3(cdiv(nst, 256)), dim3(256), 0, s, nst, out.z, w.z32);
