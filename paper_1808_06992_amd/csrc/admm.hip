@@ -373,8 +373,8 @@ constexpr double kStallFactor = 30.0;
 // parks too early and was 40 % slower.
 constexpr double kResidualWeight = 0.1;
 __global__ void k_freeze(int nb, int R, int pe, double *__restrict__ vmax, double *__restrict__ rmax,
-                         const double *__restrict__ gn, const double *__restrict__ cn, double tol,
-                         double park_tol,
+                         const double *__restrict__ gn, const double *__restrict__ zlam,
+                         const double *__restrict__ cn, double tol, double park_tol,
                          double stall_tol, int it, uint8_t *__restrict__ state,
                          int32_t *__restrict__ iters, double *__restrict__ kkt,
                          int *__restrict__ active, int *__restrict__ active_next) {
@@ -387,12 +387,14 @@ __global__ void k_freeze(int nb, int R, int pe, double *__restrict__ vmax, doubl
     if (s < nb * R) {
         int b = s / R, r = s % R;
         // an estimate with its residual term (rmax is zero after an exact
-        // evaluation)
-        const double vm = vmax[s] + (gn ? kResidualWeight * gn[b] * rmax[s] : 0.0);
+        // evaluation); at z = 0 (zlam given) the gradient is c itself, so the
+        // residual is max(0, ||c||_inf - lambda) with no product
+        const double c = cn[(size_t)b * pe + r % pe];
+        const double vm = zlam ? fmax(0.0, c - zlam[r / pe])
+                               : vmax[s] + (gn ? kResidualWeight * gn[b] * rmax[s] : 0.0);
         vmax[s] = 0.0;
         rmax[s] = 0.0;
         if (state[s] == 0) {
-            double c = cn[(size_t)b * pe + r % pe];
             double rel = c > 0.0 ? vm / c : vm;
             const double prev = kkt[s];
             kkt[s] = rel;
@@ -775,13 +777,14 @@ size_t admm_work_bytes(const AdmmProblem &P, int precision, int solver) {
 // at the start of the sweep); this check clears the other buffer.
 // With `estimate`, the maxima were left by the last iteration's epilogue (the
 // float32 KKT estimate): no product is run, and a solve that meets the
-// tolerance is parked rather than converged.
+// tolerance is parked rather than converged.  With `zero`, z = 0 (a cold
+// start) and the exact residual needs no product either.
 template <typename T>
 static void check_launch(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T *z,
                          bool only_active, double park_tol, double stall_tol, int it, AdmmOut &out,
-                         int *hact, hipEvent_t ev, int parity, bool estimate) {
+                         int *hact, hipEvent_t ev, int parity, bool estimate, bool zero = false) {
     int *act = w.active + (size_t)parity * (1 + P.nb), *act_next = w.active + (size_t)(parity ^ 1) * (1 + P.nb);
-    if (estimate) {
+    if (estimate || zero) {
     } else if (std::is_same<T, double>::value) {
         UOI_DISPATCH_FN(P.R, {
             KktEpi<double, 1, FN> epi{P.C, (const double *)z, w.state, P.lam, w.vmax, P.p, P.R, P.pe,
@@ -801,8 +804,9 @@ static void check_launch(hipStream_t s, const AdmmProblem &P, const AdmmWork &w,
     }
     int ns = P.nb * P.R;
     hipLaunchKernelGGL(k_freeze, dim3(cdiv(ns, 256)), dim3(256), 0, s, P.nb, P.R, P.pe, w.vmax, w.rmax,
-                       estimate ? (const double *)w.gn : nullptr, w.cn, estimate ? -1.0 : P.tol, park_tol,
-                       stall_tol, it, w.state, out.iters, out.kkt, act, act_next);
+                       estimate ? (const double *)w.gn : nullptr, zero ? P.lam : nullptr, w.cn,
+                       estimate ? -1.0 : P.tol, park_tol, stall_tol, it, w.state, out.iters, out.kkt, act,
+                       act_next);
     UOI_LAUNCH_CHECK();
     UOI_HIP(hipMemcpyAsync(hact, act, sizeof(int) * (1 + P.nb), hipMemcpyDeviceToHost, s));
     UOI_HIP(hipEventRecord(ev, s));
@@ -821,7 +825,7 @@ static int check_wait(hipEvent_t ev, const int *hact, int nb, std::vector<int> &
 template <typename T>
 static int sweep(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T *M, const T *h,
                  T *z, T *u, T *va, T *vb, int &it, int it_cap, double park_tol, double stall_tol,
-                 AdmmOut &out) {
+                 AdmmOut &out, bool zero_start) {
     std::vector<int> act_b;
     int *hact = pinned_ints(1 + P.nb);
     hipEvent_t ev;
@@ -886,7 +890,7 @@ static int sweep(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T
     // the first check evaluates the exact residual; the later ones of the float32
     // sweep take the estimate left by the chunk's last iteration
     constexpr bool kEstimate = std::is_same<T, float>::value;
-    check_launch<T>(s, P, w, z, true, park_tol, stall_tol, it, out, hact, ev, parity, false);
+    check_launch<T>(s, P, w, z, true, park_tol, stall_tol, it, out, hact, ev, parity, false, zero_start);
     parity ^= 1;
     int active = check_wait(ev, hact, P.nb, act_b);
     if (active > 0 && it < it_cap) {
@@ -1027,7 +1031,7 @@ void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, 
                            out.u, w.v0, w.v1);
         UOI_LAUNCH_CHECK();
         active = sweep<double>(s, P, w, w.M, w.h, out.z, out.u, w.v0, w.v1, it, P.max_iter, P.tol, 0.0,
-                               out);
+                               out, !warm);
     } else {
         // float32 phase: operator and state in float32, first KKT check in
         // float64, later ones on the iteration's estimate; solves whose estimate
@@ -1049,7 +1053,7 @@ void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, 
                            w.u32, w.vp0, w.vp1);
         UOI_LAUNCH_CHECK();
         active = sweep<float>(s, P, w, w.M32, w.h32, w.z32, w.u32, nullptr, nullptr, it, P.max_iter,
-                              P.tol * kParkFactor, P.tol * kStallFactor, out);
+                              P.tol * kParkFactor, P.tol * kStallFactor, out, !warm);
         // widen the state and finish parked / active solves in float64
         hipLaunchKernelGGL(k_f32_to_f64, dim3(cdiv(nst, 256)), dim3(256), 0, s, nst, w.z32, out.z);
         hipLaunchKernelGGL(k_f32_to_f64, dim3(cdiv(nst, 256)), dim3(256), 0, s, nst, w.u32, out.u);
@@ -1059,7 +1063,7 @@ void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, 
         UOI_LAUNCH_CHECK();
         int it64 = it;
         active = sweep<double>(s, P, w, w.M, w.h, out.z, out.u, w.v0, w.v1, it64, P.max_iter + it,
-                               P.tol, 0.0, out);
+                               P.tol, 0.0, out, false);
         it = it64;
     }
     if (stage_ms) {
