@@ -942,6 +942,18 @@ void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, 
         for (auto &e : ev) UOI_HIP(hipEventCreate(&e));
     if (stage_ms) UOI_HIP(hipEventRecord(ev[0], s));
 
+    // ||G||_inf per bootstrap for the float32 KKT estimate: one pass over G on the
+    // second stream, beside the factorization
+    const bool mixed = solver != UOI_SOLVER_PLAIN && precision != UOI_FP64;
+    AuxStream &ax = aux_stream();
+    if (mixed) {
+        UOI_HIP(hipEventRecord(ax.e0, s));
+        UOI_HIP(hipStreamWaitEvent(ax.s, ax.e0, 0));
+        UOI_HIP(hipMemsetAsync(w.gn, 0, sizeof(double) * P.nb, ax.s));
+        hipLaunchKernelGGL(k_gnorm, dim3(cdiv(P.p, 64), P.nb), dim3(256), 0, ax.s, P.p, P.G, w.gn);
+        UOI_LAUNCH_CHECK();
+        UOI_HIP(hipEventRecord(ax.e1, ax.s));
+    }
     // factor: M = (G + rho I)^{-1}, h = M C, and ||c||_inf per equation
     spd_inverse_f64(s, P.nb, P.p, P.G, P.rho, w.M, spd_work, w.M32);  // M32: mixed only
     launch_matmul_f64(s, P.nb, P.p, P.pe, w.M, P.C, w.h);
@@ -1038,8 +1050,7 @@ void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, 
         // reaches kParkFactor x the tolerance, or stalls within kStallFactor x
         // the tolerance, are parked, then verified and finished in float64.
         // (the float32 copy of M was written by the factorization)
-        UOI_HIP(hipMemsetAsync(w.gn, 0, sizeof(double) * P.nb, s));
-        hipLaunchKernelGGL(k_gnorm, dim3(cdiv(P.p, 64), P.nb), dim3(256), 0, s, P.p, P.G, w.gn);
+        UOI_HIP(hipStreamWaitEvent(s, ax.e1, 0));  // ||G||_inf (started beside the factor)
         size_t nh = (size_t)P.nb * P.p * P.pe;
         hipLaunchKernelGGL(k_f64_to_f32, dim3(cdiv(nh, 256)), dim3(256), 0, s, nh, w.h, w.h32);
         hipLaunchKernelGGL(k_f64_to_f32, dim3(cdiv(nst, 256)), dim3(256), 0, s, nst, out.z, w.z32);
