@@ -42,6 +42,7 @@ AuxStream &aux_stream() {
         UOI_HIP(hipStreamCreateWithFlags(&a.s, hipStreamNonBlocking));
         UOI_HIP(hipEventCreateWithFlags(&a.e0, hipEventDisableTiming));
         UOI_HIP(hipEventCreateWithFlags(&a.e1, hipEventDisableTiming));
+        UOI_HIP(hipEventCreateWithFlags(&a.e2, hipEventDisableTiming));
     }
     return a;
 }
@@ -319,6 +320,14 @@ static int lasso_fit(int n, int p, const double *X, const double *y, const uoi_o
     UOI_HIP(hipMemcpyAsync(lam, o->lambdas, sizeof(double) * q, hipMemcpyHostToDevice, s));
     // model selection: bootstrap rows, Gram, ADMM sweep, supports
     launch_boot_rows(s, o->seed, TAG_LASSO_BOOT, B1, n, rows);
+    // the estimation splits depend on the seed only: drawn on the second stream
+    // beside the selection stage
+    AuxStream &ax = aux_stream();
+    UOI_HIP(hipEventRecord(ax.e0, s));
+    UOI_HIP(hipStreamWaitEvent(ax.s, ax.e0, 0));
+    launch_split(ax.s, o->seed, TAG_LASSO_SPLIT, B2, n, ntr, flag);
+    launch_compact_rows(ax.s, B2, n, flag, ntr, tr, ev);
+    UOI_HIP(hipEventRecord(ax.e2, ax.s));
     {
         // the Gram of a bootstrap sample runs over its distinct rows weighted by
         // their multiplicities (about 63% of n rows) and divides by n
@@ -353,8 +362,7 @@ static int lasso_fit(int n, int p, const double *X, const double *y, const uoi_o
         E.p = pE;
         E.supp = cs;
     }
-    launch_split(s, o->seed, TAG_LASSO_SPLIT, B2, n, ntr, flag);
-    launch_compact_rows(s, B2, n, flag, ntr, tr, ev);
+    UOI_HIP(hipStreamWaitEvent(s, ax.e2, 0));  // the splits
     // evaluation products directly; training products as their complement in the
     // full-data product (the split partitions the rows), so the larger training
     // side is never gathered
@@ -462,6 +470,14 @@ static int var_fit(int T, int p, int d, const double *series, int block_len, con
     tm.mark();
     UOI_HIP(hipMemcpyAsync(lam, o->lambdas, sizeof(double) * q, hipMemcpyHostToDevice, s));
     launch_var_boot_rows(s, o->seed, B1, N, L, rows);
+    // the estimation splits depend on the seed only: drawn on the second stream
+    // beside the selection stage
+    AuxStream &ax = aux_stream();
+    UOI_HIP(hipEventRecord(ax.e0, s));
+    UOI_HIP(hipStreamWaitEvent(ax.s, ax.e0, 0));
+    launch_split(ax.s, o->seed, TAG_VAR_SPLIT, B2, nblk, nbt, flag);
+    launch_expand_blocks(ax.s, B2, nblk, N, L, flag, tr, ev, ntr, nev);
+    UOI_HIP(hipEventRecord(ax.e2, ax.s));
     {
         // distinct regression rows of each block-bootstrap sample, weighted by
         // their multiplicities
@@ -482,8 +498,7 @@ static int var_fit(int T, int p, int d, const double *series, int block_len, con
     tm.mark();
     launch_support_and(s, B1, p, R, z, supp_out);
     tm.mark();
-    launch_split(s, o->seed, TAG_VAR_SPLIT, B2, nblk, nbt, flag);
-    launch_expand_blocks(s, B2, nblk, N, L, flag, tr, ev, ntr, nev);
+    UOI_HIP(hipStreamWaitEvent(s, ax.e2, 0));  // the splits
     launch_gram_f64(s, B2, N, ev, nev, p, Xd, p, pe, Yd, p, GE, CE, nullptr, 1);
     launch_colsq(s, B2, N, ev, nev, pe, Yd, p, sE);
     launch_train_from_eval(s, B2, N, p, Xd, p, pe, Yd, p, GE, CE, 0, 0, ntr, nev, GT, CT, cw);

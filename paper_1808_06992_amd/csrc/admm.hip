@@ -1053,15 +1053,20 @@ void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, 
         UOI_HIP(hipStreamWaitEvent(s, ax.e1, 0));  // ||G||_inf (started beside the factor)
         size_t nh = (size_t)P.nb * P.p * P.pe;
         hipLaunchKernelGGL(k_f64_to_f32, dim3(cdiv(nh, 256)), dim3(256), 0, s, nh, w.h, w.h32);
-        hipLaunchKernelGGL(k_f64_to_f32, dim3(cdiv(nst, 256)), dim3(256), 0, s, nst, out.z, w.z32);
-        hipLaunchKernelGGL(k_f64_to_f32, dim3(cdiv(nst, 256)), dim3(256), 0, s, nst, out.u, w.u32);
-        // v planes: zero (rows past p stay zero), then v = z - u
+        // v planes: zero (rows past p stay zero), then v = z - u (zero at a cold start)
         const int ldk = bf3_ldk(P.p);
         const size_t np3 = (size_t)P.nb * 3 * P.R * ldk;
         UOI_HIP(hipMemsetAsync(w.vp0, 0, sizeof(__bf16) * np3, s));
         UOI_HIP(hipMemsetAsync(w.vp1, 0, sizeof(__bf16) * np3, s));
-        hipLaunchKernelGGL(k_refresh_vp, dim3(cdiv(nst, 256)), dim3(256), 0, s, P.nb, P.p, P.R, ldk, w.z32,
-                           w.u32, w.vp0, w.vp1);
+        if (warm) {
+            hipLaunchKernelGGL(k_f64_to_f32, dim3(cdiv(nst, 256)), dim3(256), 0, s, nst, out.z, w.z32);
+            hipLaunchKernelGGL(k_f64_to_f32, dim3(cdiv(nst, 256)), dim3(256), 0, s, nst, out.u, w.u32);
+            hipLaunchKernelGGL(k_refresh_vp, dim3(cdiv(nst, 256)), dim3(256), 0, s, P.nb, P.p, P.R, ldk,
+                               w.z32, w.u32, w.vp0, w.vp1);
+        } else {
+            UOI_HIP(hipMemsetAsync(w.z32, 0, sizeof(float) * nst, s));
+            UOI_HIP(hipMemsetAsync(w.u32, 0, sizeof(float) * nst, s));
+        }
         UOI_LAUNCH_CHECK();
         active = sweep<float>(s, P, w, w.M32, w.h32, w.z32, w.u32, nullptr, nullptr, it, P.max_iter,
                               P.tol * kParkFactor, P.tol * kStallFactor, out, !warm);

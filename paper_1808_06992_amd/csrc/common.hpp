@@ -49,7 +49,7 @@ int *pinned_ints(size_t n);
 // two events, for independent kernels that can run beside the caller's stream.
 struct AuxStream {
     hipStream_t s = nullptr;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
 };
 AuxStream &aux_stream();
 
