@@ -28,7 +28,7 @@ struct PoolEntry {
 };
 std::mutex g_pool_mu;
 std::map<int, PoolEntry> g_pool;
-std::map<int, PoolEntry> g_pinned;
+std::map<std::pair<int, int>, PoolEntry> g_pinned;  // (device, slot)
 }  // namespace
 
 AuxStream &aux_stream() {
@@ -47,12 +47,12 @@ AuxStream &aux_stream() {
     return a;
 }
 
-int *pinned_ints(size_t n) {
+void *pinned_slot(int slot, size_t bytes) {
     int dev = 0;
     UOI_HIP(hipGetDevice(&dev));
     std::lock_guard<std::mutex> lk(g_pool_mu);
-    PoolEntry &e = g_pinned[dev];
-    const size_t bytes = sizeof(int) * std::max<size_t>(n, 64);
+    PoolEntry &e = g_pinned[std::make_pair(dev, slot)];
+    bytes = std::max<size_t>(bytes, 256);
     if (e.cap < bytes) {
         if (e.ptr) {
             UOI_HIP(hipDeviceSynchronize());
@@ -67,8 +67,10 @@ int *pinned_ints(size_t n) {
         }
         e.cap = bytes;
     }
-    return (int *)e.ptr;
+    return e.ptr;
 }
+
+int *pinned_ints(size_t n) { return (int *)pinned_slot(kPinnedCounts, sizeof(int) * n); }
 
 void *pool_get(size_t bytes) {
     int dev = 0;
@@ -276,7 +278,7 @@ static int lasso_fit(int n, int p, const double *X, const double *y, const uoi_o
                       void *&admm_w, void *&est_w, void *&cw, int32_t *&gidx, uint64_t *&cs, double *&XU,
                       double *&bc) {
         // draws, counts, distinct rows, weights, sizes, input check flags, union size
-        rows = a.take<int32_t>((size_t)4 * B1 * n + B1 + 8);
+        rows = a.take<int32_t>((size_t)4 * B1 * n + B1 + 8 + q);  // + union count and support sizes
         G = a.take<double>((size_t)B1 * p * p);
         c = a.take<double>((size_t)B1 * p);
         lam = a.take<double>(q);
@@ -352,7 +354,8 @@ static int lasso_fit(int n, int p, const double *X, const double *y, const uoi_o
     // The refits read statistics of support columns only: when the union U of the
     // q supports is at most 3/4 of the columns, the products are formed over
     // X[:, U] and the supports renumbered; beta* is scattered back at the end.
-    const int nu = launch_support_union(s, q, p, supp_out, rows + (size_t)4 * B1 * n + B1 + 4, gidx);
+    std::vector<int32_t> sizes;
+    const int nu = launch_support_union(s, q, p, supp_out, rows + (size_t)4 * B1 * n + B1 + 4, gidx, &sizes);
     const bool compact = nu > 0 && 4 * (int64_t)nu <= 3 * (int64_t)p;
     const int pE = compact ? nu : p;
     const double *XE = X;
@@ -370,12 +373,14 @@ static int lasso_fit(int n, int p, const double *X, const double *y, const uoi_o
     launch_train_from_eval(s, B2, n, pE, XE, pE, 1, y, 1, GE, CE, ntr, nev, nullptr, nullptr, GT, CT, cw);
     tm.mark();
     E.GT = GT; E.CT = CT; E.GE = GE; E.CE = CE; E.sE = sE;
+    int *bad = (int *)pinned_slot(kPinnedFlag, sizeof(int));  // checked after the final synchronisation
     estimate(s, E, est_w, compact ? bc : beta_out, jstar_out, diag ? diag->losses : nullptr,
-             timing ? sm + 6 : nullptr);
+             timing ? sm + 6 : nullptr, &sizes, bad);
     if (compact) launch_scatter_cols(s, p, nu, gidx, bc, beta_out);
     tm.mark();
     if (diag && diag->sel_beta) transpose(s, B1, p, R, z, diag->sel_beta, true);
     UOI_HIP(hipStreamSynchronize(s));
+    if (*bad) throw Error(UOI_EINVAL, "estimation: a training Gram restricted to a support is singular");
     if (timing) {
         sm[0] = tm.between(0, 1);
         sm[4] = tm.between(2, 3);

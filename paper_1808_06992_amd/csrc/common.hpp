@@ -44,7 +44,11 @@ void *pool_get(size_t bytes);  // returns a device buffer of at least `bytes`
 void pool_release();
 // Pinned host ints for asynchronous readbacks of small results (grow-only, one
 // buffer per device, like the pool; calls that overlap on one device race).
-int *pinned_ints(size_t n);
+// Grow-only pinned host buffers per (device, slot); a slot's buffer is reused by
+// the next call that asks for it, so its contents live until then.
+enum { kPinnedCounts = 0, kPinnedLists = 1, kPinnedFlag = 2, kPinnedLarge = 3 };
+void *pinned_slot(int slot, size_t bytes);
+int *pinned_ints(size_t n);  // slot kPinnedCounts
 // A second stream of the current device (default priority, non-blocking) with
 // two events, for independent kernels that can run beside the caller's stream.
 struct AuxStream {
@@ -276,7 +280,8 @@ void launch_cnorm(hipStream_t s, int nb, int p, int pe, const double *C, double 
 void launch_support_and(hipStream_t s, int nb, int p, int R, const double *z, uint64_t *supp);
 // union of the R supports: writes its columns to gidx (increasing) and returns
 // their number (synchronises); -1 when p > 65536
-int launch_support_union(hipStream_t s, int R, int p, const uint64_t *supp, int *count, int32_t *gidx);
+int launch_support_union(hipStream_t s, int R, int p, const uint64_t *supp, int *count, int32_t *gidx,
+                         std::vector<int32_t> *sizes = nullptr);
 // supports in the union's numbering (cs[R][ceil(cnt/64)]) and XU = X[:, gidx]
 void launch_compact_design(hipStream_t s, int R, int p, int cnt, const uint64_t *supp, const int32_t *gidx,
                            uint64_t *cs, int n, const double *X, int ldx, double *XU);
@@ -296,7 +301,8 @@ struct EstimProblem {
 };
 size_t estim_work_bytes(const EstimProblem &E);
 void estimate(hipStream_t s, const EstimProblem &E, void *work, double *beta_out, int32_t *jstar,
-              double *losses_out, float *stage_ms);
+              double *losses_out, float *stage_ms, const std::vector<int32_t> *sizes = nullptr,
+              int *bad_host = nullptr);
 
 // finite check of an array; sets *flag (device int) to 1 on NaN/Inf
 void launch_finite_check(hipStream_t s, const double *x, size_t n, int *flag);

@@ -582,8 +582,12 @@ size_t estim_work_bytes(const EstimProblem &E) {
     return ar.off + 4096;
 }
 
+// sizes: the support sizes when the caller already read them back (saves a
+// host round trip); the device copy is formed here either way.  bad_host
+// (pinned): the singular-refit flag is copied there and the caller checks it
+// after synchronising the stream; without it the check happens here.
 void estimate(hipStream_t s, const EstimProblem &E, void *work, double *beta_out, int32_t *jstar,
-              double *losses_out, float *stage_ms) {
+              double *losses_out, float *stage_ms, const std::vector<int32_t> *sizes, int *bad_host) {
     const int W = (E.p + 63) / 64;
     UOI_REQUIRE(W <= 1024, "estimation: p must be <= 65536");
     // support sizes decide the solver of every column (they do not depend on k)
@@ -594,8 +598,12 @@ void estimate(hipStream_t s, const EstimProblem &E, void *work, double *beta_out
     hipLaunchKernelGGL(k_popcount, dim3(cdiv(E.R, 256)), dim3(256), 0, s, E.R, W, E.supp, cnt);
     UOI_LAUNCH_CHECK();
     std::vector<int32_t> hc(E.R);
-    UOI_HIP(hipMemcpyAsync(hc.data(), cnt, sizeof(int32_t) * E.R, hipMemcpyDeviceToHost, s));
-    UOI_HIP(hipStreamSynchronize(s));
+    if (sizes && (int)sizes->size() == E.R) {
+        hc = *sizes;
+    } else {
+        UOI_HIP(hipMemcpyAsync(hc.data(), cnt, sizeof(int32_t) * E.R, hipMemcpyDeviceToHost, s));
+        UOI_HIP(hipStreamSynchronize(s));
+    }
     std::vector<int32_t> lidx, mids;
     int smax = 0;
     for (int r = 0; r < E.R; ++r) {
@@ -608,7 +616,11 @@ void estimate(hipStream_t s, const EstimProblem &E, void *work, double *beta_out
     ar.base = (char *)work;
     ar.cap = (size_t)-1;
     EstimWork w = carve(E, nL, ar);
-    if (nL) UOI_HIP(hipMemcpyAsync(w.Lidx, lidx.data(), sizeof(int32_t) * nL, hipMemcpyHostToDevice, s));
+    if (nL) {
+        int32_t *pl = (int32_t *)pinned_slot(kPinnedLarge, sizeof(int32_t) * nL);
+        std::copy(lidx.begin(), lidx.end(), pl);
+        UOI_HIP(hipMemcpyAsync(w.Lidx, pl, sizeof(int32_t) * nL, hipMemcpyHostToDevice, s));
+    }
     UOI_HIP(hipMemsetAsync(w.flags, 0, 2 * sizeof(int), s));
 
     hipEvent_t ev[3];
@@ -630,19 +642,29 @@ void estimate(hipStream_t s, const EstimProblem &E, void *work, double *beta_out
     // the factor scratch
     if (!mids.empty()) {
         const size_t cap = mid_scratch_doubles(E);
+        // the system lists of all chunks go to disjoint parts of one pinned
+        // buffer, so no copy waits for the host and no list is overwritten early
+        const size_t nmid = mids.size() * (size_t)E.nb;
+        char *pin = (char *)pinned_slot(kPinnedLists, (sizeof(int2) + sizeof(size_t)) * nmid);
+        int2 *psys = (int2 *)pin;
+        size_t *poff = (size_t *)(pin + sizeof(int2) * nmid);
+        size_t pused = 0;
         std::vector<int2> sys;
         std::vector<size_t> off;
         size_t used = 0;
         auto flush = [&]() {
             if (sys.empty()) return;
-            UOI_HIP(hipMemcpyAsync(w.sys, sys.data(), sizeof(int2) * sys.size(), hipMemcpyHostToDevice, s));
-            UOI_HIP(hipMemcpyAsync(w.off, off.data(), sizeof(size_t) * off.size(), hipMemcpyHostToDevice, s));
+            std::copy(sys.begin(), sys.end(), psys + pused);
+            std::copy(off.begin(), off.end(), poff + pused);
+            UOI_HIP(hipMemcpyAsync(w.sys, psys + pused, sizeof(int2) * sys.size(), hipMemcpyHostToDevice, s));
+            UOI_HIP(hipMemcpyAsync(w.off, poff + pused, sizeof(size_t) * off.size(), hipMemcpyHostToDevice, s));
+            pused += sys.size();
             hipLaunchKernelGGL(k_ols_mid, dim3((unsigned)sys.size()), dim3(256), 0, s, E.p, E.pe, E.R, W,
                                E.supp, w.sys, w.off, w.Lmid, E.GT, E.CT, E.GE, E.CE, E.sE, w.Fit, w.loss,
                                w.flags);
             UOI_LAUNCH_CHECK();
-            // the host lists are reused only after the copies above have completed
-            UOI_HIP(hipStreamSynchronize(s));
+            // (the next chunk's copies into w.sys / w.off follow this launch on the
+            // stream, so the device lists are not overwritten early)
             sys.clear();
             off.clear();
             used = 0;
@@ -709,6 +731,10 @@ void estimate(hipStream_t s, const EstimProblem &E, void *work, double *beta_out
         UOI_HIP(hipEventElapsedTime(&stage_ms[0], ev[0], ev[1]));
         UOI_HIP(hipEventElapsedTime(&stage_ms[1], ev[1], ev[2]));
         for (auto &e : ev) UOI_HIP(hipEventDestroy(e));
+    }
+    if (bad_host) {
+        UOI_HIP(hipMemcpyAsync(bad_host, w.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+        return;
     }
     int bad = 0;
     UOI_HIP(hipMemcpyAsync(&bad, w.flags, sizeof(int), hipMemcpyDeviceToHost, s));

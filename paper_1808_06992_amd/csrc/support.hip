@@ -38,11 +38,19 @@ __global__ void k_support_and(int p, int R, const double *__restrict__ z, uint64
 // Union U of the supports of all R solves and its compact numbering: gidx[c] is
 // the column of compact column c (increasing), *count = |U|.  The refits of the
 // estimation step only read statistics of columns in some support, so they can
-// run on X[:, U].  One workgroup; W <= 1024 words.
+// run on X[:, U].  One workgroup; W <= 1024 words.  With sizes, sizes[r] =
+// |S_r| as well.
 __global__ __launch_bounds__(1024) void k_support_union(int R, int W, const uint64_t *__restrict__ supp,
-                                                        int *__restrict__ count, int32_t *__restrict__ gidx) {
+                                                        int *__restrict__ count, int32_t *__restrict__ gidx,
+                                                        int32_t *__restrict__ sizes) {
     __shared__ int base[1024];
     const int t = threadIdx.x;
+    if (sizes)
+        for (int r = t; r < R; r += 1024) {
+            int c = 0;
+            for (int w = 0; w < W; ++w) c += __popcll(supp[(size_t)r * W + w]);
+            sizes[r] = c;
+        }
     uint64_t u = 0;
     if (t < W)
         for (int r = 0; r < R; ++r) u |= supp[(size_t)r * W + t];
@@ -96,15 +104,19 @@ __global__ void k_scatter_cols(int pc, const int32_t *__restrict__ gidx, const d
     if (c < pc) dst[gidx[c]] = src[c];
 }
 
-int launch_support_union(hipStream_t s, int R, int p, const uint64_t *supp, int *count, int32_t *gidx) {
+int launch_support_union(hipStream_t s, int R, int p, const uint64_t *supp, int *count, int32_t *gidx,
+                         std::vector<int32_t> *sizes) {
     const int W = (p + 63) / 64;
     if (W > 1024) return -1;
-    hipLaunchKernelGGL(k_support_union, dim3(1), dim3(1024), 0, s, R, W, supp, count, gidx);
+    // count[0] = |U|; with sizes, count[1 + r] = |S_r|, read back in the same copy
+    hipLaunchKernelGGL(k_support_union, dim3(1), dim3(1024), 0, s, R, W, supp, count, gidx,
+                       sizes ? count + 1 : nullptr);
     UOI_LAUNCH_CHECK();
-    int h = 0;
-    UOI_HIP(hipMemcpyAsync(&h, count, sizeof(int), hipMemcpyDeviceToHost, s));
+    std::vector<int32_t> h(sizes ? 1 + R : 1);
+    UOI_HIP(hipMemcpyAsync(h.data(), count, sizeof(int32_t) * h.size(), hipMemcpyDeviceToHost, s));
     UOI_HIP(hipStreamSynchronize(s));
-    return h;
+    if (sizes) sizes->assign(h.begin() + 1, h.end());
+    return h[0];
 }
 
 void launch_compact_design(hipStream_t s, int R, int p, int cnt, const uint64_t *supp, const int32_t *gidx,
