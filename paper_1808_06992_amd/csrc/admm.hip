@@ -892,9 +892,11 @@ static int sweep(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T
     constexpr bool kEstimate = std::is_same<T, float>::value;
     check_launch<T>(s, P, w, z, true, park_tol, stall_tol, it, out, hact, ev, parity, false, zero_start);
     parity ^= 1;
+    // the first chunk is queued behind the first check as well
+    const bool spec0 = it < it_cap;
+    if (spec0) run_chunk(std::min(P.check_every, it_cap - it));
     int active = check_wait(ev, hact, P.nb, act_b);
-    if (active > 0 && it < it_cap) {
-        run_chunk(std::min(P.check_every, it_cap - it));
+    if (active > 0 && spec0) {
         account(pend.back());
         it = itq;
         for (;;) {
