@@ -365,6 +365,12 @@ __global__ __launch_bounds__(256) void k_cnorm(int p, int pe, const double *__re
 constexpr double kStallRatio = 0.7;
 constexpr double kParkFactor = 5.0;
 constexpr double kStallFactor = 30.0;
+// Float64 finish: iterations between its first (exact) check and the second.
+// Solves parked at 5x the tolerance mostly converge within 3 float64 iterations;
+// the later chunks have the usual length (2 / 3 / 4 / 10 gave 4.6 / 3.5 / 3.6 /
+// 4.4 ms for the LASSO fit's ADMM stage; shorter later chunks slow the long
+// float64 phase of the VAR fit).
+constexpr int kFinishFirst = 3;
 // Weight of ||G||_inf ||x - z||_inf in the float32 KKT estimate.  1 gives a
 // strict bound, which float32 rounding of x - z keeps above the parking
 // threshold for some solves; G (x - z) is far below that worst case in
@@ -818,14 +824,15 @@ static int check_wait(hipEvent_t ev, const int *hact, int nb, std::vector<int> &
     return act_b[0];
 }
 
-// ADMM iterations in chunks of check_every, each followed by a KKT check.  The
+// ADMM iterations in chunks (the first of first_every iterations, the later
+// ones of every), each followed by a KKT check.  The
 // next chunk is queued before the host reads the previous check (it changes
 // only solves that the check left active), so the GPU does not idle while the
 // counts travel back; a chunk queued after the last solve froze does no work.
 template <typename T>
 static int sweep(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T *M, const T *h,
                  T *z, T *u, T *va, T *vb, int &it, int it_cap, double park_tol, double stall_tol,
-                 AdmmOut &out, bool zero_start) {
+                 AdmmOut &out, bool zero_start, int every, int first_every) {
     std::vector<int> act_b;
     int *hact = pinned_ints(1 + P.nb);
     hipEvent_t ev;
@@ -894,7 +901,7 @@ static int sweep(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T
     parity ^= 1;
     // the first chunk is queued behind the first check as well
     const bool spec0 = it < it_cap;
-    if (spec0) run_chunk(std::min(P.check_every, it_cap - it));
+    if (spec0) run_chunk(std::min(first_every, it_cap - it));
     int active = check_wait(ev, hact, P.nb, act_b);
     if (active > 0 && spec0) {
         account(pend.back());
@@ -903,7 +910,7 @@ static int sweep(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T
             check_launch<T>(s, P, w, z, true, park_tol, stall_tol, it, out, hact, ev, parity, kEstimate);
             parity ^= 1;
             const bool spec = it < it_cap;
-            if (spec) run_chunk(std::min(P.check_every, it_cap - it));
+            if (spec) run_chunk(std::min(every, it_cap - it));
             active = check_wait(ev, hact, P.nb, act_b);
             if (active == 0 || !spec) break;
             account(pend.back());  // the queued chunk ran with this active set
@@ -1045,7 +1052,7 @@ void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, 
                            out.u, w.v0, w.v1);
         UOI_LAUNCH_CHECK();
         active = sweep<double>(s, P, w, w.M, w.h, out.z, out.u, w.v0, w.v1, it, P.max_iter, P.tol, 0.0,
-                               out, !warm);
+                               out, !warm, P.check_every, P.check_every);
     } else {
         // float32 phase: operator and state in float32, first KKT check in
         // float64, later ones on the iteration's estimate; solves whose estimate
@@ -1071,7 +1078,8 @@ void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, 
         }
         UOI_LAUNCH_CHECK();
         active = sweep<float>(s, P, w, w.M32, w.h32, w.z32, w.u32, nullptr, nullptr, it, P.max_iter,
-                              P.tol * kParkFactor, P.tol * kStallFactor, out, !warm);
+                              P.tol * kParkFactor, P.tol * kStallFactor, out, !warm, P.check_every,
+                              P.check_every);
         // widen the state and finish parked / active solves in float64
         hipLaunchKernelGGL(k_f32_to_f64, dim3(cdiv(nst, 256)), dim3(256), 0, s, nst, w.z32, out.z);
         hipLaunchKernelGGL(k_f32_to_f64, dim3(cdiv(nst, 256)), dim3(256), 0, s, nst, w.u32, out.u);
@@ -1081,7 +1089,7 @@ void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, 
         UOI_LAUNCH_CHECK();
         int it64 = it;
         active = sweep<double>(s, P, w, w.M, w.h, out.z, out.u, w.v0, w.v1, it64, P.max_iter + it,
-                               P.tol, 0.0, out, false);
+                               P.tol, 0.0, out, false, P.check_every, std::min(P.check_every, kFinishFirst));
         it = it64;
     }
     if (stage_ms) {
