@@ -59,8 +59,9 @@ enum {
 /* precision of the selection sweep */
 enum {
     UOI_FP64 = 0,   /* float64 Gram, factor, ADMM and KKT                        */
-    UOI_MIXED = 1   /* float64 Gram and factor, float32 ADMM state and operator,
-                       float64 KKT checks and float64 finishing iterations        */
+    UOI_MIXED = 1   /* float64 Gram and factor, float32 ADMM state and operator
+                       (solves parked on a KKT estimate), float64 KKT checks
+                       decide convergence after float64 finishing iterations     */
 };
 
 /* ADMM warm start */
