@@ -361,7 +361,8 @@ __global__ __launch_bounds__(256) void k_cnorm(int p, int pe, const double *__re
 // residual fell by less than kStallRatio since the previous check (it has
 // reached what float32 arithmetic resolves).  kkt[] holds the previous value
 // (initialised to a huge number).  iters[] is -1 while a solve is active, -(it+2)
-// while it is parked at iteration it, and its iteration count once converged.
+// once it has been parked at iteration it (kept while it is finished in
+// float64), and its iteration count once converged.
 constexpr double kStallRatio = 0.7;
 constexpr double kParkFactor = 5.0;
 constexpr double kStallFactor = 30.0;
@@ -371,6 +372,10 @@ constexpr double kStallFactor = 30.0;
 // 4.4 ms for the LASSO fit's ADMM stage; shorter later chunks slow the long
 // float64 phase of the VAR fit).
 constexpr int kFinishFirst = 3;
+// The float64 finish starts without a check: nearly every bootstrap holds some
+// parked solve above the tolerance, so its tile runs anyway, and the check after
+// the first chunk decides all of them (0.1 ms less than checking first).
+constexpr bool kFinishFirstCheck = false;
 // Weight of ||G||_inf ||x - z||_inf in the float32 KKT estimate.  1 gives a
 // strict bound, which float32 rounding of x - z keeps above the parking
 // threshold for some solves; G (x - z) is far below that worst case in
@@ -381,7 +386,7 @@ constexpr double kResidualWeight = 0.1;
 __global__ void k_freeze(int nb, int R, int pe, double *__restrict__ vmax, double *__restrict__ rmax,
                          const double *__restrict__ gn, const double *__restrict__ zlam,
                          const double *__restrict__ cn, double tol, double park_tol,
-                         double stall_tol, int it, uint8_t *__restrict__ state,
+                         double stall_tol, int it, int it_base, uint8_t *__restrict__ state,
                          int32_t *__restrict__ iters, double *__restrict__ kkt,
                          int *__restrict__ active, int *__restrict__ active_next) {
     // active[0] = all solves still active, active[1 + b] = those of bootstrap b;
@@ -406,16 +411,15 @@ __global__ void k_freeze(int nb, int R, int pe, double *__restrict__ vmax, doubl
             kkt[s] = rel;
             const int32_t ip = iters[s];
             if (rel <= tol) {
-                // a parked solve that meets the tolerance without further
-                // iterations keeps the iteration at which it was parked
+                // a parked solve counts the iterations up to its parking and those
+                // of this sweep (which began at it_base)
                 state[s] = 1;
-                iters[s] = ip <= -2 ? -ip - 2 : it;
+                iters[s] = ip <= -2 ? -ip - 2 + (it - it_base) : it;
             } else if (rel <= park_tol || (rel <= stall_tol && rel > kStallRatio * prev)) {
                 state[s] = 2;
                 if (ip == -1) iters[s] = -it - 2;  // provisional, still counted as unconverged
             } else {
                 act = true;
-                if (ip <= -2) iters[s] = -1;
                 atomicAdd(&active[1 + b], 1);
             }
         }
@@ -787,7 +791,7 @@ size_t admm_work_bytes(const AdmmProblem &P, int precision, int solver) {
 // start) and the exact residual needs no product either.
 template <typename T>
 static void check_launch(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T *z,
-                         bool only_active, double park_tol, double stall_tol, int it, AdmmOut &out,
+                         bool only_active, double park_tol, double stall_tol, int it, int it_base, AdmmOut &out,
                          int *hact, hipEvent_t ev, int parity, bool estimate, bool zero = false) {
     int *act = w.active + (size_t)parity * (1 + P.nb), *act_next = w.active + (size_t)(parity ^ 1) * (1 + P.nb);
     if (estimate || zero) {
@@ -811,7 +815,7 @@ static void check_launch(hipStream_t s, const AdmmProblem &P, const AdmmWork &w,
     int ns = P.nb * P.R;
     hipLaunchKernelGGL(k_freeze, dim3(cdiv(ns, 256)), dim3(256), 0, s, P.nb, P.R, P.pe, w.vmax, w.rmax,
                        estimate ? (const double *)w.gn : nullptr, zero ? P.lam : nullptr, w.cn,
-                       estimate ? -1.0 : P.tol, park_tol, stall_tol, it, w.state, out.iters, out.kkt, act,
+                       estimate ? -1.0 : P.tol, park_tol, stall_tol, it, it_base, w.state, out.iters, out.kkt, act,
                        act_next);
     UOI_LAUNCH_CHECK();
     UOI_HIP(hipMemcpyAsync(hact, act, sizeof(int) * (1 + P.nb), hipMemcpyDeviceToHost, s));
@@ -832,7 +836,7 @@ static int check_wait(hipEvent_t ev, const int *hact, int nb, std::vector<int> &
 template <typename T>
 static int sweep(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T *M, const T *h,
                  T *z, T *u, T *va, T *vb, int &it, int it_cap, double park_tol, double stall_tol,
-                 AdmmOut &out, bool zero_start, int every, int first_every) {
+                 AdmmOut &out, bool zero_start, int every, int first_every, bool first_check = true) {
     std::vector<int> act_b;
     int *hact = pinned_ints(1 + P.nb);
     hipEvent_t ev;
@@ -895,19 +899,32 @@ static int sweep(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T
     UOI_HIP(hipMemsetAsync(w.active, 0, sizeof(int) * 2 * (1 + P.nb), s));
     int parity = 0;
     // the first check evaluates the exact residual; the later ones of the float32
-    // sweep take the estimate left by the chunk's last iteration
+    // sweep take the estimate left by the chunk's last iteration.  Without a
+    // first check (first_check false) every solve runs the first chunk.
     constexpr bool kEstimate = std::is_same<T, float>::value;
-    check_launch<T>(s, P, w, z, true, park_tol, stall_tol, it, out, hact, ev, parity, false, zero_start);
-    parity ^= 1;
-    // the first chunk is queued behind the first check as well
-    const bool spec0 = it < it_cap;
-    if (spec0) run_chunk(std::min(first_every, it_cap - it));
-    int active = check_wait(ev, hact, P.nb, act_b);
-    if (active > 0 && spec0) {
+    const int it_base = it;
+    int active = 0;
+    bool enter = false;
+    if (first_check) {
+        check_launch<T>(s, P, w, z, true, park_tol, stall_tol, it, it_base, out, hact, ev, parity, false,
+                        zero_start);
+        parity ^= 1;
+        // the first chunk is queued behind the first check as well
+        const bool spec0 = it < it_cap;
+        if (spec0) run_chunk(std::min(first_every, it_cap - it));
+        active = check_wait(ev, hact, P.nb, act_b);
+        enter = active > 0 && spec0;
+    } else {
+        act_b.assign(1 + P.nb, P.R);  // for the traffic account: all active
+        act_b[0] = P.nb * P.R;
+        run_chunk(std::min(first_every, it_cap - it));
+        enter = true;
+    }
+    if (enter) {
         account(pend.back());
         it = itq;
         for (;;) {
-            check_launch<T>(s, P, w, z, true, park_tol, stall_tol, it, out, hact, ev, parity, kEstimate);
+            check_launch<T>(s, P, w, z, true, park_tol, stall_tol, it, it_base, out, hact, ev, parity, kEstimate);
             parity ^= 1;
             const bool spec = it < it_cap;
             if (spec) run_chunk(std::min(every, it_cap - it));
@@ -1089,7 +1106,8 @@ void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, 
         UOI_LAUNCH_CHECK();
         int it64 = it;
         active = sweep<double>(s, P, w, w.M, w.h, out.z, out.u, w.v0, w.v1, it64, P.max_iter + it,
-                               P.tol, 0.0, out, false, P.check_every, std::min(P.check_every, kFinishFirst));
+                               P.tol, 0.0, out, false, P.check_every, std::min(P.check_every, kFinishFirst),
+                               kFinishFirstCheck);
         it = it64;
     }
     if (stage_ms) {
