@@ -366,11 +366,11 @@ __global__ __launch_bounds__(256) void k_cnorm(int p, int pe, const double *__re
 constexpr double kStallRatio = 0.7;
 constexpr double kParkFactor = 5.0;
 constexpr double kStallFactor = 30.0;
-// Float64 finish: iterations between its first (exact) check and the second.
-// Solves parked at 5x the tolerance mostly converge within 3 float64 iterations;
-// the later chunks have the usual length (2 / 3 / 4 / 10 gave 4.6 / 3.5 / 3.6 /
-// 4.4 ms for the LASSO fit's ADMM stage; shorter later chunks slow the long
-// float64 phase of the VAR fit).
+// Float64 finish: the length of its first chunk.  Solves parked at 5x the
+// tolerance mostly converge within 3 float64 iterations; the later chunks have
+// the usual length (2 / 3 / 4 / 10 gave 4.6 / 3.5 / 3.6 / 4.4 ms for the LASSO
+// fit's ADMM stage; shorter later chunks slow the long float64 phase of the VAR
+// fit).
 constexpr int kFinishFirst = 3;
 // The float64 finish starts without a check: nearly every bootstrap holds some
 // parked solve above the tolerance, so its tile runs anyway, and the check after
