@@ -162,6 +162,36 @@ def test_admm_matches_oracle(api, orc, solver, precision, relax, n, p, q):
             assert np.array_equal((z[k, j] != 0)[dec], (ref[j] != 0)[dec])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_admm_cold_start_zero_solutions(api, orc, precision):
+    """lambda >= ||c||_inf: z = 0 is the solution, and a cold start meets the KKT
+    bound at iteration 0 (its first check needs no product: the gradient at z = 0
+    is c).  The other lambdas converge to the oracle's solutions."""
+    pr = synth.lasso_random(300, 70, 8, 3, q=6)
+    Gs, cs = [], []
+    for k in range(2):
+        G, c = orc.gram(pr.X, pr.y, orc.boot_rows(0, k, 300))
+        Gs.append(G)
+        cs.append(c)
+    Gs, cs = np.array(Gs), np.array(cs)
+    cmax = np.abs(cs).max(axis=1)
+    lams = np.array([2.0 * cmax.max(), 1.0 * cmax.max() + 1e-9, 0.5 * cmax.min(), 0.2 * cmax.min()])
+    res = api.lasso_solve_batch(cuda(Gs), cuda(cs), lams, kkt_tol=1e-9, precision=precision)
+    assert res["status"] == 0
+    z, its, kkt = (res[k].cpu().numpy() for k in ("z", "iters", "kkt"))
+    for k in range(2):
+        for j, lam in enumerate(lams):
+            if lam >= cmax[k]:
+                assert its[k, j] == 0 and np.all(z[k, j] == 0.0)
+                assert kkt[k, j] == 0.0
+            else:
+                assert its[k, j] > 0
+                assert orc.kkt(Gs[k], cs[k], lam, z[k, j]) <= 1e-8
+                ref, st = orc.lasso_cd(Gs[k], cs[k], lam, tol=1e-13)
+                assert st >= 0
+                assert np.abs(z[k, j] - ref).max() <= 1e-6 * max(np.abs(ref).max(), 1e-300)
+
+
 def test_admm_reports_nonconvergence(api, orc):
     pr = synth.lasso_random(200, 50, 10, 1, q=4)
     G, c = orc.gram(pr.X, pr.y, np.arange(200, dtype=np.int32))
