@@ -339,8 +339,8 @@ def main():
         make_traffic(*a.make_traffic)
         return
     if a.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}); "
-              "multi-GPU sharding is described in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py: runs on one GPU (asked for --gpus {a.gpus}); splitting the bootstraps "
+              "over several GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_1808_06992_amd import _lib as api
