@@ -72,6 +72,38 @@ void *pinned_slot(int slot, size_t bytes) {
 
 int *pinned_ints(size_t n) { return (int *)pinned_slot(kPinnedCounts, sizeof(int) * n); }
 
+namespace {
+std::mutex g_event_mu;
+std::map<int, std::vector<hipEvent_t>> g_events;  // free timing events per device
+}  // namespace
+
+hipEvent_t event_take() {
+    int dev = 0;
+    UOI_HIP(hipGetDevice(&dev));
+    {
+        std::lock_guard<std::mutex> lk(g_event_mu);
+        std::vector<hipEvent_t> &v = g_events[dev];
+        if (!v.empty()) {
+            hipEvent_t e = v.back();
+            v.pop_back();
+            return e;
+        }
+    }
+    hipEvent_t e;
+    UOI_HIP(hipEventCreate(&e));
+    return e;
+}
+
+void event_give(hipEvent_t e) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipEventDestroy(e);
+        return;
+    }
+    std::lock_guard<std::mutex> lk(g_event_mu);
+    g_events[dev].push_back(e);
+}
+
 void *pool_get(size_t bytes) {
     int dev = 0;
     UOI_HIP(hipGetDevice(&dev));
@@ -205,8 +237,8 @@ struct KernelTimer {
     KernelTimer(hipStream_t s_, uoi_kstat *k_) : s(s_), k(k_) {}
     void start() {
         if (!k) return;
-        UOI_HIP(hipEventCreate(&e0));
-        UOI_HIP(hipEventCreate(&e1));
+        e0 = event_take();
+        e1 = event_take();
         UOI_HIP(hipEventRecord(e0, s));
     }
     void stop() {
@@ -222,8 +254,8 @@ struct KernelTimer {
         k->launches += 1;
     }
     ~KernelTimer() {
-        if (e0) (void)hipEventDestroy(e0);
-        if (e1) (void)hipEventDestroy(e1);
+        if (e0) event_give(e0);
+        if (e1) event_give(e1);
     }
 };
 
@@ -234,8 +266,7 @@ struct Timer {
     Timer(hipStream_t s_, bool on_) : s(s_), on(on_) {}
     void mark() {
         if (!on) return;
-        hipEvent_t e;
-        UOI_HIP(hipEventCreate(&e));
+        hipEvent_t e = event_take();
         UOI_HIP(hipEventRecord(e, s));
         ev.push_back(e);
     }
@@ -245,7 +276,7 @@ struct Timer {
         return ms;
     }
     ~Timer() {
-        for (auto e : ev) (void)hipEventDestroy(e);
+        for (auto e : ev) event_give(e);
     }
 };
 
@@ -346,6 +377,8 @@ static int lasso_fit(int n, int p, const double *X, const double *y, const uoi_o
     P.lam = lam;
     AdmmOut out{z, u, diag && diag->iters ? diag->iters : its, diag && diag->kkt ? diag->kkt : kkt, 0, 0,
                 timing && diag ? diag->kstat : nullptr, 0};
+    DeferredTiming dtm;  // stage and kernel times, read after the final synchronisation
+    out.dt = &dtm;
     admm_solve(s, P, o->precision, o->solver, admm_w, false, out, timing ? sm + 1 : nullptr);
     tm.mark();
     launch_support_and(s, B1, p, R, z, supp_out);
@@ -375,11 +408,12 @@ static int lasso_fit(int n, int p, const double *X, const double *y, const uoi_o
     E.GT = GT; E.CT = CT; E.GE = GE; E.CE = CE; E.sE = sE;
     int *bad = (int *)pinned_slot(kPinnedFlag, sizeof(int));  // checked after the final synchronisation
     estimate(s, E, est_w, compact ? bc : beta_out, jstar_out, diag ? diag->losses : nullptr,
-             timing ? sm + 6 : nullptr, &sizes, bad);
+             timing ? sm + 6 : nullptr, &sizes, bad, &dtm);
     if (compact) launch_scatter_cols(s, p, nu, gidx, bc, beta_out);
     tm.mark();
     if (diag && diag->sel_beta) transpose(s, B1, p, R, z, diag->sel_beta, true);
     UOI_HIP(hipStreamSynchronize(s));
+    dtm.resolve();
     if (*bad) throw Error(UOI_EINVAL, "estimation: a training Gram restricted to a support is singular");
     if (timing) {
         sm[0] = tm.between(0, 1);
@@ -499,6 +533,8 @@ static int var_fit(int T, int p, int d, const double *series, int block_len, con
     P.lam = lam;
     AdmmOut out{z, u, diag && diag->iters ? diag->iters : its, diag && diag->kkt ? diag->kkt : kkt, 0, 0,
                 timing && diag ? diag->kstat : nullptr, 0};
+    DeferredTiming dtm;  // stage and kernel times, read after the final synchronisation
+    out.dt = &dtm;
     admm_solve(s, P, o->precision, o->solver, admm_w, false, out, timing ? sm + 1 : nullptr);
     tm.mark();
     launch_support_and(s, B1, p, R, z, supp_out);
@@ -509,11 +545,13 @@ static int var_fit(int T, int p, int d, const double *series, int block_len, con
     launch_train_from_eval(s, B2, N, p, Xd, p, pe, Yd, p, GE, CE, 0, 0, ntr, nev, GT, CT, cw);
     tm.mark();
     E.GT = GT; E.CT = CT; E.GE = GE; E.CE = CE; E.sE = sE;
-    estimate(s, E, est_w, A_out, jstar_out, diag ? diag->losses : nullptr, timing ? sm + 6 : nullptr);
+    estimate(s, E, est_w, A_out, jstar_out, diag ? diag->losses : nullptr, timing ? sm + 6 : nullptr, nullptr,
+             nullptr, &dtm);
     tm.mark();
     UOI_HIP(hipMemsetAsync(mu_out, 0, sizeof(double) * p, s));
     if (diag && diag->sel_beta) transpose(s, B1, p, R, z, diag->sel_beta, true);
     UOI_HIP(hipStreamSynchronize(s));
+    dtm.resolve();
     if (timing) {
         sm[0] = tm.between(0, 1);
         sm[4] = tm.between(2, 3);

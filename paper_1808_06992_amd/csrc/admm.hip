@@ -851,14 +851,14 @@ static int sweep(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T
         bool used;
     };
     std::vector<Pending> pend;
+    // chunk timing goes to the caller's deferred record, else to a local one
+    // resolved at the end of the sweep
+    DeferredTiming local;
+    DeferredTiming *dt = ks ? (out.dt ? out.dt : &local) : nullptr;
     int itq = it;  // iterations queued so far
     auto run_chunk = [&](int n) {
         Pending pc{nullptr, nullptr, 0.0, 0.0, n, false};
-        if (ks) {
-            UOI_HIP(hipEventCreate(&pc.e0));
-            UOI_HIP(hipEventCreate(&pc.e1));
-            UOI_HIP(hipEventRecord(pc.e0, s));
-        }
+        if (dt) pc.e0 = dt->mark(s);
         for (int t = 0; t < n; ++t) {
             T *vin = (itq & 1) ? vb : va;
             T *vout = (itq & 1) ? va : vb;
@@ -878,7 +878,7 @@ static int sweep(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T
             });
             ++itq;
         }
-        if (ks) UOI_HIP(hipEventRecord(pc.e1, s));
+        if (dt) pc.e1 = dt->mark(s);
         pend.push_back(pc);
     };
     // algorithmic traffic and work of a chunk run with the active set act_b
@@ -934,19 +934,12 @@ static int sweep(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T
             it = itq;
         }
     }
-    if (ks) {
-        if (!pend.empty()) UOI_HIP(hipEventSynchronize(pend.back().e1));
-        for (Pending &pc : pend) {
-            if (pc.used) {
-                float ms = 0.f;
-                UOI_HIP(hipEventElapsedTime(&ms, pc.e0, pc.e1));
-                ks->ms += ms;
-                ks->bytes += pc.bytes;
-                ks->flops += pc.flops;
-                ks->launches += pc.n;
-            }
-            UOI_HIP(hipEventDestroy(pc.e0));
-            UOI_HIP(hipEventDestroy(pc.e1));
+    if (dt) {
+        for (Pending &pc : pend)
+            if (pc.used) dt->kernel(pc.e0, pc.e1, ks, pc.bytes, pc.flops, pc.n);
+        if (dt == &local && !pend.empty()) {
+            UOI_HIP(hipEventSynchronize(pend.back().e1));
+            local.resolve();
         }
     }
     UOI_HIP(hipEventDestroy(ev));
@@ -963,10 +956,11 @@ void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, 
     const size_t nst = (size_t)P.nb * P.p * P.R;
     const int ns = P.nb * P.R;
 
-    hipEvent_t ev[3];
-    if (stage_ms)
-        for (auto &e : ev) UOI_HIP(hipEventCreate(&e));
-    if (stage_ms) UOI_HIP(hipEventRecord(ev[0], s));
+    // stage times: recorded in the caller's deferred record, else resolved here
+    DeferredTiming local;
+    DeferredTiming *dt = stage_ms ? (out.dt ? out.dt : &local) : nullptr;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    if (dt) ev[0] = dt->mark(s);
 
     // ||G||_inf per bootstrap for the float32 KKT estimate: one pass over G on the
     // second stream, beside the factorization
@@ -984,7 +978,7 @@ void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, 
     spd_inverse_f64(s, P.nb, P.p, P.G, P.rho, w.M, spd_work, w.M32);  // M32: mixed only
     launch_matmul_f64(s, P.nb, P.p, P.pe, w.M, P.C, w.h);
     launch_cnorm(s, P.nb, P.p, P.pe, P.C, w.cn);
-    if (stage_ms) UOI_HIP(hipEventRecord(ev[1], s));
+    if (dt) ev[1] = dt->mark(s);
 
     UOI_HIP(hipMemsetAsync(w.state, 0, ns, s));
     UOI_HIP(hipMemsetAsync(out.kkt, 0x7f, sizeof(double) * ns, s));  // "previous" KKT: huge
@@ -1110,12 +1104,14 @@ void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, 
                                kFinishFirstCheck);
         it = it64;
     }
-    if (stage_ms) {
-        UOI_HIP(hipEventRecord(ev[2], s));
-        UOI_HIP(hipEventSynchronize(ev[2]));
-        UOI_HIP(hipEventElapsedTime(&stage_ms[0], ev[0], ev[1]));
-        UOI_HIP(hipEventElapsedTime(&stage_ms[1], ev[1], ev[2]));
-        for (auto &e : ev) UOI_HIP(hipEventDestroy(e));
+    if (dt) {
+        ev[2] = dt->mark(s);
+        dt->time(ev[0], ev[1], &stage_ms[0]);
+        dt->time(ev[1], ev[2], &stage_ms[1]);
+        if (dt == &local) {
+            UOI_HIP(hipEventSynchronize(ev[2]));
+            local.resolve();
+        }
     }
     // unconverged solves and the largest iteration count, read by admm_finish_stats
     UOI_HIP(hipMemsetAsync(w.stat, 0, 2 * sizeof(int), s));

@@ -254,6 +254,54 @@ struct AdmmProblem {
     double relax;        // over-relaxation alpha (1 = plain scaled ADMM)
 };
 
+// Timing events of the current device, reused across calls (an event may be
+// handed out again while its last record is still pending: recording it again
+// simply replaces that record).
+hipEvent_t event_take();
+void event_give(hipEvent_t e);
+
+// Timing of a fit: events are recorded as the work is queued and read only
+// after the fit's final synchronisation (resolve), so measuring adds no host
+// wait.  Spans write elapsed milliseconds to a float or add to a kernel record.
+struct DeferredTiming {
+    struct Span {
+        hipEvent_t a, b;
+        float *ms;       // elapsed time, or
+        uoi_kstat *ks;   // accumulated kernel record
+        double bytes, flops;
+        int launches;
+    };
+    std::vector<Span> spans;
+    std::vector<hipEvent_t> owned;
+    hipEvent_t mark(hipStream_t s) {
+        hipEvent_t e = event_take();  // pooled: creating events costs host time
+        owned.push_back(e);
+        UOI_HIP(hipEventRecord(e, s));
+        return e;
+    }
+    void time(hipEvent_t a, hipEvent_t b, float *ms) { spans.push_back(Span{a, b, ms, nullptr, 0, 0, 0}); }
+    void kernel(hipEvent_t a, hipEvent_t b, uoi_kstat *k, double bytes, double flops, int launches) {
+        spans.push_back(Span{a, b, nullptr, k, bytes, flops, launches});
+    }
+    void resolve() {  // after the stream has synchronised
+        for (const Span &sp : spans) {
+            float ms = 0.f;
+            UOI_HIP(hipEventElapsedTime(&ms, sp.a, sp.b));
+            if (sp.ms) *sp.ms = ms;
+            if (sp.ks) {
+                sp.ks->ms += ms;
+                sp.ks->bytes += sp.bytes;
+                sp.ks->flops += sp.flops;
+                sp.ks->launches += sp.launches;
+            }
+        }
+        spans.clear();
+    }
+    ~DeferredTiming() {
+        for (hipEvent_t e : owned) event_give(e);
+    }
+};
+
 struct AdmmOut {
     double *z;           // [nb][p][R]   (feature-major state)
     double *u;           // [nb][p][R]
@@ -264,6 +312,7 @@ struct AdmmOut {
     uoi_kstat *kstat;    // [UOI_KSTAT_N] accumulated when non-null (timing runs)
     int64_t warm_used;   // solves started from the network
     int *dstat;          // device: [0] unconverged solves, [1] largest iteration count
+    DeferredTiming *dt = nullptr;  // where timing runs record their events (else resolved in place)
 };
 // Reads the counts that admm_solve left in out.dstat (after the caller's final
 // synchronisation of the stream).
@@ -302,7 +351,7 @@ struct EstimProblem {
 size_t estim_work_bytes(const EstimProblem &E);
 void estimate(hipStream_t s, const EstimProblem &E, void *work, double *beta_out, int32_t *jstar,
               double *losses_out, float *stage_ms, const std::vector<int32_t> *sizes = nullptr,
-              int *bad_host = nullptr);
+              int *bad_host = nullptr, DeferredTiming *dt = nullptr);
 
 // finite check of an array; sets *flag (device int) to 1 on NaN/Inf
 void launch_finite_check(hipStream_t s, const double *x, size_t n, int *flag);

@@ -585,9 +585,11 @@ size_t estim_work_bytes(const EstimProblem &E) {
 // sizes: the support sizes when the caller already read them back (saves a
 // host round trip); the device copy is formed here either way.  bad_host
 // (pinned): the singular-refit flag is copied there and the caller checks it
-// after synchronising the stream; without it the check happens here.
+// after synchronising the stream; without it the check happens here.  dt: where
+// the stage times are recorded (resolved by the caller), else resolved here.
 void estimate(hipStream_t s, const EstimProblem &E, void *work, double *beta_out, int32_t *jstar,
-              double *losses_out, float *stage_ms, const std::vector<int32_t> *sizes, int *bad_host) {
+              double *losses_out, float *stage_ms, const std::vector<int32_t> *sizes, int *bad_host,
+              DeferredTiming *dt) {
     const int W = (E.p + 63) / 64;
     UOI_REQUIRE(W <= 1024, "estimation: p must be <= 65536");
     // support sizes decide the solver of every column (they do not depend on k)
@@ -623,11 +625,11 @@ void estimate(hipStream_t s, const EstimProblem &E, void *work, double *beta_out
     }
     UOI_HIP(hipMemsetAsync(w.flags, 0, 2 * sizeof(int), s));
 
-    hipEvent_t ev[3];
-    if (stage_ms) {
-        for (auto &e : ev) UOI_HIP(hipEventCreate(&e));
-        UOI_HIP(hipEventRecord(ev[0], s));
-    }
+    // stage times: recorded in the caller's deferred record, else resolved here
+    DeferredTiming local;
+    DeferredTiming *dtm = stage_ms ? (dt ? dt : &local) : nullptr;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    if (dtm) ev[0] = dtm->mark(s);
     // small supports, on a second stream beside the mid-size ones (they write
     // disjoint systems' results; the mid-size launch ends with a few long systems)
     AuxStream &ax = aux_stream();
@@ -718,19 +720,21 @@ void estimate(hipStream_t s, const EstimProblem &E, void *work, double *beta_out
                            E.supp, w.Lidx, w.X, E.GE, E.CE, E.sE, w.Fit, w.loss);
         UOI_LAUNCH_CHECK();
     }
-    if (stage_ms) UOI_HIP(hipEventRecord(ev[1], s));
+    if (dtm) ev[1] = dtm->mark(s);
     hipLaunchKernelGGL(k_argmin, dim3(E.nb), dim3(64), 0, s, E.q, E.pe, w.loss, w.Lq, jstar);
     hipLaunchKernelGGL(k_average, dim3(cdiv((size_t)E.pe * E.p, 256)), dim3(256), 0, s, E.nb, E.p, E.pe,
                        E.R, w.Fit, jstar, beta_out);
     UOI_LAUNCH_CHECK();
     if (losses_out)
         UOI_HIP(hipMemcpyAsync(losses_out, w.Lq, sizeof(double) * E.nb * E.q, hipMemcpyDeviceToDevice, s));
-    if (stage_ms) {
-        UOI_HIP(hipEventRecord(ev[2], s));
-        UOI_HIP(hipEventSynchronize(ev[2]));
-        UOI_HIP(hipEventElapsedTime(&stage_ms[0], ev[0], ev[1]));
-        UOI_HIP(hipEventElapsedTime(&stage_ms[1], ev[1], ev[2]));
-        for (auto &e : ev) UOI_HIP(hipEventDestroy(e));
+    if (dtm) {
+        ev[2] = dtm->mark(s);
+        dtm->time(ev[0], ev[1], &stage_ms[0]);
+        dtm->time(ev[1], ev[2], &stage_ms[1]);
+        if (dtm == &local) {
+            UOI_HIP(hipEventSynchronize(ev[2]));
+            local.resolve();
+        }
     }
     if (bad_host) {
         UOI_HIP(hipMemcpyAsync(bad_host, w.flags, sizeof(int), hipMemcpyDeviceToHost, s));
