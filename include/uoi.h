@@ -24,7 +24,8 @@
  *    Argument validation (sizes, lambda ordering, NaN/Inf in the data) happens
  *    before any result is written.  UOI_ENOCONV means every output was written
  *    but at least one ADMM solve did not reach opts->kkt_tol within max_iter;
- *    the per-solve flags in uoi_diag say which.
+ *    the per-solve flags in uoi_diag say which (or, for the refits of the
+ *    estimation step, uoi_diag.n_refit_unconverged counts them).
  *  - Objective scaling: for a sample of m rows the LASSO minimised is
  *        (1/(2m)) * sum_rows (y - x'b)^2 + lambda * ||b||_1,
  *    which has the same minimiser as Eq. (2) with penalty 2*m*lambda.  Lambdas
@@ -106,6 +107,11 @@ typedef struct uoi_opts {
                               scaled ADMM).  With alpha, the z- and u-updates use
                               alpha*x + (1-alpha)*z_old in place of x (Boyd et al. 2011,
                               Sec. 3.4.3); the fixed point, hence the solution, is the same. */
+    int32_t cg_max_iter;   /* iteration cap of the conjugate-gradient refits of supports with
+                              more than 256 members, >= 1 (default 4000).  A refit still above
+                              its tolerance (relative residual 1e-13) at the cap is used as it
+                              is, counted in uoi_diag.n_refit_unconverged, and the fit returns
+                              UOI_ENOCONV.                                                      */
 } uoi_opts;
 
 /* Per-kernel totals gathered with UOI_FLAG_TIMING: device time from hipEvents
@@ -146,6 +152,9 @@ typedef struct uoi_diag {
     float stage_ms[8];  /* with UOI_FLAG_TIMING: index/gram, factor, admm, verify,
                            support, estimation-gram, ols, loss+average                   */
     uoi_kstat kstat[UOI_KSTAT_N]; /* with UOI_FLAG_TIMING: per-kernel totals (see below) */
+    int64_t n_refit_unconverged;  /* estimation refits (split x support [x equation]) that
+                                     conjugate gradients left above its tolerance at
+                                     opts.cg_max_iter (the fit then returns UOI_ENOCONV)     */
 } uoi_diag;
 
 /* Fill *o with the defaults listed above (B1 = B2 = q = 0, lambdas = NULL). */

@@ -97,14 +97,14 @@ def index(r: int, m: int) -> int:
 
 
 def boot_rows(seed: int, k: int, n: int) -> np.ndarray:
-    """Alg. 1 'generate bootstrap sample': n rows drawn with replacement."""
+    """Alg. 1 selection loop, the sample T^k: n rows drawn with replacement."""
     out = np.empty(n, np.int32)
     lib().orc_boot_rows(seed, k, n, _p(out))
     return out
 
 
 def split_rows(seed: int, k: int, n: int, num: int = 4, den: int = 5):
-    """Alg. 1 estimation samples: train/eval partition, each ascending."""
+    """Alg. 1 estimation loop: train/eval partition of the rows, each ascending."""
     ntr = int(lib().orc_split_count(n, num, den))
     tr = np.empty(max(ntr, 1), np.int32)
     ev = np.empty(max(n - ntr, 1), np.int32)
@@ -117,7 +117,7 @@ def var_block_len(N: int) -> int:
 
 
 def var_boot_rows(seed: int, k: int, N: int, L: int) -> np.ndarray:
-    """Sec. III-A.2 block bootstrap: moving blocks of regression rows."""
+    """Alg. 2 block bootstrap (Sec. III-A.2): moving blocks of regression rows."""
     out = np.empty(N, np.int32)
     lib().orc_var_boot_rows(seed, k, N, L, _p(out))
     return out

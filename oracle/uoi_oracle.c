@@ -38,7 +38,7 @@
 #include "uoi_oracle.h"
 
 /* ------------------------------------------------------------------------ */
-/* Random indices.  The paper only says "generate bootstrap sample"; the     */
+/* Random indices.  Alg. 1 leaves the resampling scheme open; here the      */
 /* index stream is a counter-based SplitMix64 (Steele, Lea, Flood 2014)      */
 /* keyed by (seed, tag, bootstrap, position), mapped to [0, m) by Lemire's   */
 /* multiply-shift.                                                            */
@@ -62,7 +62,7 @@ uint32_t orc_index(uint64_t r, uint32_t m)
     return (uint32_t)(((unsigned __int128)r * (unsigned __int128)m) >> 64);
 }
 
-/* Alg. 1, "generate bootstrap sample T^k": n row draws with replacement. */
+/* Alg. 1 selection loop, the sample T^k: n row draws with replacement. */
 void orc_boot_rows(uint64_t seed, int k, int n, int32_t *rows)
 {
     for (int i = 0; i < n; ++i)
@@ -108,8 +108,8 @@ int orc_split_count(int n, int num, int den)
     return (int)(((int64_t)n * num) / den);
 }
 
-/* Alg. 1, "bootstrap samples for training and evaluation": a partition of
- * the n rows, training = floor(n*num/den) rows. */
+/* Alg. 1 estimation loop: the training and evaluation samples, read here as a
+ * partition of the n rows without replacement, training = floor(n*num/den) rows. */
 void orc_split_rows(uint64_t seed, int k, int n, int num, int den, int32_t *train, int32_t *eval)
 {
     keyed_split(seed, ORC_TAG_LASSO_SPLIT, k, n, orc_split_count(n, num, den), train, eval);
@@ -125,8 +125,8 @@ int orc_var_block_len(int N)
 
 int orc_var_nblocks(int N, int L) { return (N + L - 1) / L; }
 
-/* Sec. III-A.2: "randomly selecting time series blocks" -- moving blocks of
- * L consecutive regression rows, nb = ceil(N/L) starts, truncated to N rows. */
+/* Alg. 2 block bootstrap (Sec. III-A.2): moving blocks of L consecutive
+ * regression rows at random starts, nb = ceil(N/L) blocks, truncated to N rows. */
 void orc_var_boot_rows(uint64_t seed, int k, int N, int L, int32_t *rows)
 {
     int nb = orc_var_nblocks(N, L);

@@ -44,7 +44,7 @@ class Opts(C.Structure):
         ("train_num", C.c_int32), ("train_den", C.c_int32),
         ("precision", C.c_int32), ("warm_start", C.c_int32), ("solver", C.c_int32),
         ("flags", C.c_uint32), ("stream", C.c_void_p), ("mlp", C.c_void_p),
-        ("relax", C.c_double),
+        ("relax", C.c_double), ("cg_max_iter", C.c_int32),
     ]
 
 
@@ -61,7 +61,7 @@ class Diag(C.Structure):
         ("iters", C.c_void_p), ("kkt", C.c_void_p), ("sel_beta", C.c_void_p),
         ("losses", C.c_void_p), ("n_solves", C.c_int64), ("n_unconverged", C.c_int64),
         ("max_iters", C.c_int32), ("warm_used", C.c_int64), ("stage_ms", C.c_float * 8),
-        ("kstat", KStat * 4),
+        ("kstat", KStat * 4), ("n_refit_unconverged", C.c_int64),
     ]
 
 
@@ -163,7 +163,8 @@ def _ptr(t):
 
 def make_opts(lambdas, *, B1=1, B2=1, seed=0, rho=1.0, kkt_tol=1e-6, max_iter=20000,
               check_every=10, train=(4, 5), precision="fp64", solver="batched",
-              warm_start="cold", timing=False, stream="current", mlp=None, relax=1.0):
+              warm_start="cold", timing=False, stream="current", mlp=None, relax=1.0,
+              cg_max_iter=4000):
     lam = np.ascontiguousarray(np.asarray(lambdas, dtype=np.float64))
     o = Opts()
     load().uoi_default_opts(C.byref(o))
@@ -178,6 +179,7 @@ def make_opts(lambdas, *, B1=1, B2=1, seed=0, rho=1.0, kkt_tol=1e-6, max_iter=20
     o.warm_start = WARM[warm_start]
     o.flags = UOI_FLAG_TIMING if timing else 0
     o.relax = float(relax)
+    o.cg_max_iter = int(cg_max_iter)
     o.stream = _stream() if stream == "current" else C.c_void_p(stream)
     if mlp is not None:
         o.mlp = mlp.handle
@@ -212,6 +214,7 @@ def lasso_fit(X: torch.Tensor, y: torch.Tensor, lambdas, B1: int, B2: int, seed:
                                   _ptr(jstar), C.byref(d)))
     out["status"] = code
     out["n_unconverged"] = int(d.n_unconverged)
+    out["n_refit_unconverged"] = int(d.n_refit_unconverged)
     out["max_iters"] = int(d.max_iters)
     out["warm_used"] = int(d.warm_used)
     out["stage_ms"] = dict(zip(STAGES, list(d.stage_ms)))
@@ -247,6 +250,7 @@ def var_fit(series: torch.Tensor, lambdas, B1: int, B2: int, seed: int = 0, *, b
                                 _ptr(supp), _ptr(jstar), C.byref(d)))
     out["status"] = code
     out["n_unconverged"] = int(d.n_unconverged)
+    out["n_refit_unconverged"] = int(d.n_refit_unconverged)
     out["max_iters"] = int(d.max_iters)
     out["stage_ms"] = dict(zip(STAGES, list(d.stage_ms)))
     out["kstat"] = kstats(d)
@@ -265,10 +269,11 @@ def lasso_solve_batch(G: torch.Tensor, c: torch.Tensor, lambdas, *, z0=None, u0=
     u = torch.empty((nb, q, p), dtype=torch.float64, device=dev)
     its = torch.empty((nb, q), dtype=torch.int32, device=dev)
     kkt = torch.empty((nb, q), dtype=torch.float64, device=dev)
-    code = _check(L.uoi_lasso_solve_batch(nb, p, _ptr(G), _ptr(c), C.byref(o),
-                                          _ptr(None if z0 is None else _dev(z0)),
-                                          _ptr(None if u0 is None else _dev(u0)),
-                                          _ptr(z), _ptr(u), _ptr(its), _ptr(kkt)))
+    fn = L.uoi_lasso_solve_batch
+    code = _check(fn(nb, p, _ptr(G), _ptr(c), C.byref(o),
+                     _ptr(None if z0 is None else _dev(z0)),
+                     _ptr(None if u0 is None else _dev(u0)),
+                     _ptr(z), _ptr(u), _ptr(its), _ptr(kkt)))
     return dict(z=z, u=u, iters=its, kkt=kkt, status=code)
 
 

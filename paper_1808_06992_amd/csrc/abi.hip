@@ -162,6 +162,7 @@ static void check_opts(const uoi_opts *o, bool need_boot) {
     UOI_REQUIRE(std::isfinite(o->kkt_tol) && o->kkt_tol > 0.0, "kkt_tol must be > 0");
     UOI_REQUIRE(o->max_iter >= 1, "max_iter must be >= 1");
     UOI_REQUIRE(o->check_every >= 1, "check_every must be >= 1");
+    UOI_REQUIRE(o->cg_max_iter >= 1, "cg_max_iter must be >= 1");
     UOI_REQUIRE(std::isfinite(o->relax) && o->relax >= 1.0 && o->relax <= 1.95,
                 "relax must be in [1, 1.95]");
     UOI_REQUIRE(o->precision == UOI_FP64 || o->precision == UOI_MIXED, "unknown precision");
@@ -299,7 +300,7 @@ static int lasso_fit(int n, int p, const double *X, const double *y, const uoi_o
     const int B1 = o->B1, B2 = o->B2, q = o->q, R = q;
     AdmmProblem P{B1, p, q, 1, R, nullptr, nullptr, nullptr, o->rho, o->kkt_tol, o->max_iter,
                   o->check_every, o->warm_start == UOI_MLP ? o->mlp : nullptr, o->relax};
-    EstimProblem E{B2, p, 1, q, R, nullptr, nullptr, nullptr, nullptr, nullptr, supp_out};
+    EstimProblem E{B2, p, 1, q, R, nullptr, nullptr, nullptr, nullptr, nullptr, supp_out, o->cg_max_iter};
     size_t nst = (size_t)B1 * p * R;
     // size the scratch arena
     Arena ar;
@@ -406,15 +407,17 @@ static int lasso_fit(int n, int p, const double *X, const double *y, const uoi_o
     launch_train_from_eval(s, B2, n, pE, XE, pE, 1, y, 1, GE, CE, ntr, nev, nullptr, nullptr, GT, CT, cw);
     tm.mark();
     E.GT = GT; E.CT = CT; E.GE = GE; E.CE = CE; E.sE = sE;
-    int *bad = (int *)pinned_slot(kPinnedFlag, sizeof(int));  // checked after the final synchronisation
+    // [0] singular refit, [1] refits left unconverged: read after the final synchronisation
+    int *eflags = (int *)pinned_slot(kPinnedFlag, 2 * sizeof(int));
     estimate(s, E, est_w, compact ? bc : beta_out, jstar_out, diag ? diag->losses : nullptr,
-             timing ? sm + 6 : nullptr, &sizes, bad, &dtm);
+             timing ? sm + 6 : nullptr, &sizes, eflags, &dtm);
     if (compact) launch_scatter_cols(s, p, nu, gidx, bc, beta_out);
     tm.mark();
     if (diag && diag->sel_beta) transpose(s, B1, p, R, z, diag->sel_beta, true);
     UOI_HIP(hipStreamSynchronize(s));
     dtm.resolve();
-    if (*bad) throw Error(UOI_EINVAL, "estimation: a training Gram restricted to a support is singular");
+    if (eflags[0]) throw Error(UOI_EINVAL, "estimation: a training Gram restricted to a support is singular");
+    const int refit_noconv = eflags[1];
     if (timing) {
         sm[0] = tm.between(0, 1);
         sm[4] = tm.between(2, 3);
@@ -430,9 +433,10 @@ static int lasso_fit(int n, int p, const double *X, const double *y, const uoi_o
         diag->n_unconverged = out.unconverged;
         diag->max_iters = out.max_iters;
         diag->warm_used = out.warm_used;
+        diag->n_refit_unconverged = refit_noconv;
         std::memcpy(diag->stage_ms, sm, sizeof(sm));
     }
-    return out.unconverged ? UOI_ENOCONV : UOI_OK;
+    return out.unconverged || refit_noconv ? UOI_ENOCONV : UOI_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -460,7 +464,7 @@ static int var_fit(int T, int p, int d, const double *series, int block_len, con
     UOI_REQUIRE(o->warm_start == UOI_COLD, "warm start by network is for UoI_LASSO only");
     AdmmProblem P{B1, p, q, pe, R, nullptr, nullptr, nullptr, o->rho, o->kkt_tol, o->max_iter,
                   o->check_every, nullptr, o->relax};
-    EstimProblem E{B2, p, pe, q, R, nullptr, nullptr, nullptr, nullptr, nullptr, supp_out};
+    EstimProblem E{B2, p, pe, q, R, nullptr, nullptr, nullptr, nullptr, nullptr, supp_out, o->cg_max_iter};
     size_t nst = (size_t)B1 * p * R;
     auto layout = [&](Arena &a, int32_t *&rows, double *&G, double *&C, double *&lam, double *&z,
                       double *&u, int32_t *&its, double *&kkt, uint8_t *&flag, int32_t *&tr,
@@ -545,13 +549,16 @@ static int var_fit(int T, int p, int d, const double *series, int block_len, con
     launch_train_from_eval(s, B2, N, p, Xd, p, pe, Yd, p, GE, CE, 0, 0, ntr, nev, GT, CT, cw);
     tm.mark();
     E.GT = GT; E.CT = CT; E.GE = GE; E.CE = CE; E.sE = sE;
+    int *eflags = (int *)pinned_slot(kPinnedFlag, 2 * sizeof(int));
     estimate(s, E, est_w, A_out, jstar_out, diag ? diag->losses : nullptr, timing ? sm + 6 : nullptr, nullptr,
-             nullptr, &dtm);
+             eflags, &dtm);
     tm.mark();
     UOI_HIP(hipMemsetAsync(mu_out, 0, sizeof(double) * p, s));
     if (diag && diag->sel_beta) transpose(s, B1, p, R, z, diag->sel_beta, true);
     UOI_HIP(hipStreamSynchronize(s));
     dtm.resolve();
+    if (eflags[0]) throw Error(UOI_EINVAL, "estimation: a training Gram restricted to a support is singular");
+    const int refit_noconv = eflags[1];
     if (timing) {
         sm[0] = tm.between(0, 1);
         sm[4] = tm.between(2, 3);
@@ -568,22 +575,30 @@ static int var_fit(int T, int p, int d, const double *series, int block_len, con
         diag->n_unconverged = out.unconverged;
         diag->max_iters = out.max_iters;
         diag->warm_used = out.warm_used;
+        diag->n_refit_unconverged = refit_noconv;
         std::memcpy(diag->stage_ms, sm, sizeof(sm));
     }
-    return out.unconverged ? UOI_ENOCONV : UOI_OK;
+    return out.unconverged || refit_noconv ? UOI_ENOCONV : UOI_OK;
 }
 
 // ---------------------------------------------------------------------------
-static int solve_batch(int nb, int p, const double *G, const double *c, const uoi_opts *o,
-                       const double *z0, const double *u0, double *z_out, double *u_out,
-                       int32_t *iters, double *kkt) {
+// With scratch_cap > 0 the scratch memory is the caller-provided buffer
+// scratch (device, at least scratch_cap bytes): nothing is allocated, and
+// sizes beyond the buffer are rejected before any device work.
+int solve_batch(int nb, int p, const double *G, const double *c, const uoi_opts *o, const double *z0,
+                const double *u0, double *z_out, double *u_out, int32_t *iters, double *kkt,
+                void *(*scratch)(), size_t scratch_cap) {
     check_opts(o, false);
     UOI_REQUIRE(nb >= 1 && p >= 1, "need nb >= 1 and p >= 1");
     UOI_REQUIRE(G && c && z_out, "NULL input or output pointer");
+    const bool no_alloc = scratch_cap > 0;
+    UOI_REQUIRE(!no_alloc || o->warm_start == UOI_COLD,
+                "the allocation-free entry point starts cold (no warm start by network)");
     hipStream_t s = (hipStream_t)o->stream;
     const int q = o->q, R = q;
     AdmmProblem P{nb, p, q, 1, R, G, c, nullptr, o->rho, o->kkt_tol, o->max_iter, o->check_every,
                   o->warm_start == UOI_MLP ? o->mlp : nullptr, o->relax};
+    P.no_alloc = no_alloc;
     size_t nst = (size_t)nb * p * R;
     auto layout = [&](Arena &a, double *&lam, double *&z, double *&u, int32_t *&its, double *&kk,
                       void *&w) {
@@ -599,9 +614,13 @@ static int solve_batch(int nb, int p, const double *G, const double *c, const uo
     void *w;
     Arena ar;
     layout(ar, lam, z, u, its, kk, w);
+    if (no_alloc)
+        UOI_REQUIRE(ar.off <= scratch_cap,
+                    "problem needs " + std::to_string(ar.off) + " bytes of scratch; the static buffer of the "
+                    "allocation-free entry point holds " + std::to_string(scratch_cap));
     Arena A;
     A.cap = ar.off;
-    A.base = (char *)pool_get(ar.off);
+    A.base = (char *)(no_alloc ? scratch() : pool_get(ar.off));
     layout(A, lam, z, u, its, kk, w);
     UOI_HIP(hipMemcpyAsync(lam, o->lambdas, sizeof(double) * q, hipMemcpyHostToDevice, s));
     P.lam = lam;
@@ -621,23 +640,6 @@ static int solve_batch(int nb, int p, const double *G, const double *c, const uo
     return out.unconverged ? UOI_ENOCONV : UOI_OK;
 }
 
-template <class F>
-static int guarded(F &&f) {
-    try {
-        set_last_error("");
-        return f();
-    } catch (const Error &e) {
-        set_last_error(e.what());
-        return e.code;
-    } catch (const std::exception &e) {
-        set_last_error(e.what());
-        return UOI_EHIP;
-    } catch (...) {
-        set_last_error("unknown error");
-        return UOI_EHIP;
-    }
-}
-
 }  // namespace uoi
 
 using namespace uoi;
@@ -654,6 +656,7 @@ void uoi_default_opts(uoi_opts *o) {
     o->train_num = 4;
     o->train_den = 5;
     o->relax = 1.0;
+    o->cg_max_iter = 4000;
     o->precision = UOI_FP64;
     o->warm_start = UOI_COLD;
     o->solver = UOI_SOLVER_BATCHED;
@@ -674,7 +677,7 @@ int uoi_var_fit(int32_t T, int32_t p, int32_t d, const double *series, int32_t b
 int uoi_lasso_solve_batch(int32_t nb, int32_t p, const double *G, const double *c, const uoi_opts *o,
                           const double *z0, const double *u0, double *z_out, double *u_out,
                           int32_t *iters, double *kkt) {
-    return guarded([&] { return solve_batch(nb, p, G, c, o, z0, u0, z_out, u_out, iters, kkt); });
+    return guarded([&] { return solve_batch(nb, p, G, c, o, z0, u0, z_out, u_out, iters, kkt, nullptr, 0); });
 }
 
 int uoi_gram(int32_t nb, int32_t m, const int32_t *rows, int32_t p, const double *X, int32_t ldx,

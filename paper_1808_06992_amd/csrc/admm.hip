@@ -366,6 +366,13 @@ __global__ __launch_bounds__(256) void k_cnorm(int p, int pe, const double *__re
 constexpr double kStallRatio = 0.7;
 constexpr double kParkFactor = 5.0;
 constexpr double kStallFactor = 30.0;
+// The float32 iteration's KKT estimate levels off at the resolution of its
+// float32 state (about 3e-8 to 1e-6 relative, depending on |beta| / ||c||_inf),
+// so the parking window never goes below these floors: with a tolerance under
+// them, solves park at the float32 resolution and the float64 finish carries
+// them the rest of the way.  At tolerances of 1e-7 and above the factors rule.
+constexpr double kParkFloor = 5e-7;
+constexpr double kStallFloor = 3e-5;
 // Float64 finish: the length of its first chunk.  Solves parked at 5x the
 // tolerance mostly converge within 3 float64 iterations; the later chunks have
 // the usual length (2 / 3 / 4 / 10 gave 4.6 / 3.5 / 3.6 / 4.4 ms for the LASSO
@@ -433,10 +440,12 @@ __global__ void k_fill_i32(size_t n, int32_t v, int32_t *__restrict__ a) {
     if (i < n) a[i] = v;
 }
 
-// stat[0] += solves with a negative (unconverged) count, stat[1] = max count
-__global__ void k_iter_stats(int n, const int32_t *__restrict__ its, int *__restrict__ stat) {
+// stat[0] += solves with a negative (unconverged) count, stat[1] = max count;
+// an unconverged count (-1 active, -(it+2) parked) is reported as -1
+__global__ void k_iter_stats(int n, int32_t *__restrict__ its, int *__restrict__ stat) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int v = i < n ? its[i] : 0;
+    if (i < n && v < -1) its[i] = -1;
     const unsigned long long bal = __ballot(i < n && v < 0);
     int m = v > 0 ? v : 0;
     for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o));
@@ -819,11 +828,14 @@ static void check_launch(hipStream_t s, const AdmmProblem &P, const AdmmWork &w,
                        act_next);
     UOI_LAUNCH_CHECK();
     UOI_HIP(hipMemcpyAsync(hact, act, sizeof(int) * (1 + P.nb), hipMemcpyDeviceToHost, s));
-    UOI_HIP(hipEventRecord(ev, s));
+    if (ev) UOI_HIP(hipEventRecord(ev, s));
 }
 
-static int check_wait(hipEvent_t ev, const int *hact, int nb, std::vector<int> &act_b) {
-    UOI_HIP(hipEventSynchronize(ev));
+// Without an event (the allocation-free entry point) the host waits for the
+// whole stream, including a chunk queued behind the check.
+static int check_wait(hipStream_t s, hipEvent_t ev, const int *hact, int nb, std::vector<int> &act_b) {
+    if (ev) UOI_HIP(hipEventSynchronize(ev));
+    else UOI_HIP(hipStreamSynchronize(s));
     act_b.assign(hact, hact + 1 + nb);
     return act_b[0];
 }
@@ -838,9 +850,18 @@ static int sweep(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T
                  T *z, T *u, T *va, T *vb, int &it, int it_cap, double park_tol, double stall_tol,
                  AdmmOut &out, bool zero_start, int every, int first_every, bool first_check = true) {
     std::vector<int> act_b;
-    int *hact = pinned_ints(1 + P.nb);
-    hipEvent_t ev;
-    UOI_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    // the active counts come back through pinned memory marked by an event; the
+    // allocation-free entry point reads them into ordinary host memory instead
+    std::vector<int> hact_plain;
+    int *hact = nullptr;
+    hipEvent_t ev = nullptr;
+    if (P.no_alloc) {
+        hact_plain.assign(1 + P.nb, 0);
+        hact = hact_plain.data();
+    } else {
+        hact = pinned_ints(1 + P.nb);
+        UOI_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    }
     uoi_kstat *ks = out.kstat ? &out.kstat[std::is_same<T, double>::value ? UOI_KSTAT_ADMM64
                                                                            : UOI_KSTAT_ADMM32]
                               : nullptr;
@@ -912,7 +933,7 @@ static int sweep(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T
         // the first chunk is queued behind the first check as well
         const bool spec0 = it < it_cap;
         if (spec0) run_chunk(std::min(first_every, it_cap - it));
-        active = check_wait(ev, hact, P.nb, act_b);
+        active = check_wait(s, ev, hact, P.nb, act_b);
         enter = active > 0 && spec0;
     } else {
         act_b.assign(1 + P.nb, P.R);  // for the traffic account: all active
@@ -928,7 +949,7 @@ static int sweep(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T
             parity ^= 1;
             const bool spec = it < it_cap;
             if (spec) run_chunk(std::min(every, it_cap - it));
-            active = check_wait(ev, hact, P.nb, act_b);
+            active = check_wait(s, ev, hact, P.nb, act_b);
             if (active == 0 || !spec) break;
             account(pend.back());  // the queued chunk ran with this active set
             it = itq;
@@ -942,7 +963,7 @@ static int sweep(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T
             local.resolve();
         }
     }
-    UOI_HIP(hipEventDestroy(ev));
+    if (ev) UOI_HIP(hipEventDestroy(ev));
     return active;
 }
 
@@ -965,14 +986,19 @@ void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, 
     // ||G||_inf per bootstrap for the float32 KKT estimate: one pass over G on the
     // second stream, beside the factorization
     const bool mixed = solver != UOI_SOLVER_PLAIN && precision != UOI_FP64;
-    AuxStream &ax = aux_stream();
+    // (the allocation-free entry point creates no second stream: same stream)
+    AuxStream *ax = P.no_alloc ? nullptr : &aux_stream();
     if (mixed) {
-        UOI_HIP(hipEventRecord(ax.e0, s));
-        UOI_HIP(hipStreamWaitEvent(ax.s, ax.e0, 0));
-        UOI_HIP(hipMemsetAsync(w.gn, 0, sizeof(double) * P.nb, ax.s));
-        hipLaunchKernelGGL(k_gnorm, dim3(cdiv(P.p, 64), P.nb), dim3(256), 0, ax.s, P.p, P.G, w.gn);
+        hipStream_t gs = s;
+        if (ax) {
+            UOI_HIP(hipEventRecord(ax->e0, s));
+            UOI_HIP(hipStreamWaitEvent(ax->s, ax->e0, 0));
+            gs = ax->s;
+        }
+        UOI_HIP(hipMemsetAsync(w.gn, 0, sizeof(double) * P.nb, gs));
+        hipLaunchKernelGGL(k_gnorm, dim3(cdiv(P.p, 64), P.nb), dim3(256), 0, gs, P.p, P.G, w.gn);
         UOI_LAUNCH_CHECK();
-        UOI_HIP(hipEventRecord(ax.e1, ax.s));
+        if (ax) UOI_HIP(hipEventRecord(ax->e1, ax->s));
     }
     // factor: M = (G + rho I)^{-1}, h = M C, and ||c||_inf per equation
     spd_inverse_f64(s, P.nb, P.p, P.G, P.rho, w.M, spd_work, w.M32);  // M32: mixed only
@@ -987,6 +1013,7 @@ void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, 
     out.dstat = w.stat;
     out.warm_used = 0;
     if (P.mlp) {
+        UOI_REQUIRE(!P.no_alloc, "the allocation-free entry point starts cold");
         // network start for every (bootstrap, lambda); falls back to cold per solve
         int nin = 0, nout = 0;
         mlp_dims(P.mlp, &nin, &nout);
@@ -1070,7 +1097,7 @@ void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, 
         // reaches kParkFactor x the tolerance, or stalls within kStallFactor x
         // the tolerance, are parked, then verified and finished in float64.
         // (the float32 copy of M was written by the factorization)
-        UOI_HIP(hipStreamWaitEvent(s, ax.e1, 0));  // ||G||_inf (started beside the factor)
+        if (ax) UOI_HIP(hipStreamWaitEvent(s, ax->e1, 0));  // ||G||_inf (started beside the factor)
         size_t nh = (size_t)P.nb * P.p * P.pe;
         hipLaunchKernelGGL(k_f64_to_f32, dim3(cdiv(nh, 256)), dim3(256), 0, s, nh, w.h, w.h32);
         // v planes: zero (rows past p stay zero), then v = z - u (zero at a cold start)
@@ -1088,8 +1115,15 @@ void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, 
             UOI_HIP(hipMemsetAsync(w.u32, 0, sizeof(float) * nst, s));
         }
         UOI_LAUNCH_CHECK();
-        active = sweep<float>(s, P, w, w.M32, w.h32, w.z32, w.u32, nullptr, nullptr, it, P.max_iter,
-                              P.tol * kParkFactor, P.tol * kStallFactor, out, !warm, P.check_every,
+        // max_iter bounds the two phases together: the float32 phase may take at
+        // most half of it (solves still active then go on in float64), and the
+        // float64 finish runs up to max_iter on the shared iteration counter, so
+        // no solve's count (float32 iterations up to its parking plus those of
+        // the finish) exceeds max_iter.
+        const int cap32 = P.max_iter - P.max_iter / 2;
+        active = sweep<float>(s, P, w, w.M32, w.h32, w.z32, w.u32, nullptr, nullptr, it, cap32,
+                              std::max(P.tol * kParkFactor, kParkFloor),
+                              std::max(P.tol * kStallFactor, kStallFloor), out, !warm, P.check_every,
                               P.check_every);
         // widen the state and finish parked / active solves in float64
         hipLaunchKernelGGL(k_f32_to_f64, dim3(cdiv(nst, 256)), dim3(256), 0, s, nst, w.z32, out.z);
@@ -1099,7 +1133,7 @@ void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, 
                            out.u, w.v0, w.v1);
         UOI_LAUNCH_CHECK();
         int it64 = it;
-        active = sweep<double>(s, P, w, w.M, w.h, out.z, out.u, w.v0, w.v1, it64, P.max_iter + it,
+        active = sweep<double>(s, P, w, w.M, w.h, out.z, out.u, w.v0, w.v1, it64, P.max_iter,
                                P.tol, 0.0, out, false, P.check_every, std::min(P.check_every, kFinishFirst),
                                kFinishFirstCheck);
         it = it64;

@@ -37,6 +37,25 @@ struct Error : std::runtime_error {
 
 void set_last_error(const std::string &m);
 
+// Runs an entry point's body: no exception crosses the C ABI; an error becomes
+// its status code and the thread's last-error message.
+template <class F>
+int guarded(F &&f) {
+    try {
+        set_last_error("");
+        return f();
+    } catch (const Error &e) {
+        set_last_error(e.what());
+        return e.code;
+    } catch (const std::exception &e) {
+        set_last_error(e.what());
+        return UOI_EHIP;
+    } catch (...) {
+        set_last_error("unknown error");
+        return UOI_EHIP;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Scratch pool: one grow-only device allocation per device, carved by Arena.
 // ---------------------------------------------------------------------------
@@ -252,6 +271,7 @@ struct AdmmProblem {
     int check_every;
     uoi_mlp *mlp;        // warm start by network (LASSO: pe == 1), or nullptr
     double relax;        // over-relaxation alpha (1 = plain scaled ADMM)
+    bool no_alloc = false;  // no pinned memory, events or second stream (host waits instead)
 };
 
 // Timing events of the current device, reused across calls (an event may be
@@ -322,6 +342,13 @@ size_t admm_work_bytes(const AdmmProblem &P, int precision, int solver);
 void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, void *work,
                 bool warm, AdmmOut &out, float *stage_ms);
 
+// The batched LASSO solves of uoi_lasso_solve_batch (abi.hip).  With
+// scratch_cap > 0, scratch() returns the caller's device buffer of that many
+// bytes and nothing is allocated (the allocation-free entry point).
+int solve_batch(int nb, int p, const double *G, const double *c, const uoi_opts *o, const double *z0,
+                const double *u0, double *z_out, double *u_out, int32_t *iters, double *kkt,
+                void *(*scratch)(), size_t scratch_cap);
+
 // per-(b, e) ||c||_inf
 void launch_cnorm(hipStream_t s, int nb, int p, int pe, const double *C, double *cn);
 
@@ -347,11 +374,12 @@ struct EstimProblem {
     const double *CE;      // [nb][p][pe]
     const double *sE;      // [nb][pe] mean squares of the responses on evaluation rows
     const uint64_t *supp;  // [R][W]
+    int cg_max_iter;       // iteration cap of the conjugate-gradient refits
 };
 size_t estim_work_bytes(const EstimProblem &E);
 void estimate(hipStream_t s, const EstimProblem &E, void *work, double *beta_out, int32_t *jstar,
-              double *losses_out, float *stage_ms, const std::vector<int32_t> *sizes = nullptr,
-              int *bad_host = nullptr, DeferredTiming *dt = nullptr);
+              double *losses_out, float *stage_ms, const std::vector<int32_t> *sizes, int *flags_host,
+              DeferredTiming *dt = nullptr);
 
 // finite check of an array; sets *flag (device int) to 1 on NaN/Inf
 void launch_finite_check(hipStream_t s, const double *x, size_t n, int *flag);

@@ -32,7 +32,6 @@ constexpr int kMid = 256;    // blocked Cholesky with the factor in global scrat
 constexpr int kPW = 16;      // panel width of the blocked Cholesky
 constexpr size_t kMidScratch = (size_t)256 << 20;  // bytes of factor storage per launch
 constexpr double kCgTol = 1e-13;
-constexpr int kCgMaxIter = 4000;
 }
 
 __global__ void k_popcount(int R, int W, const uint64_t *__restrict__ supp, int32_t *__restrict__ cnt) {
@@ -476,6 +475,14 @@ __global__ void k_cg_scalars(int n, double tol2, uint8_t *__restrict__ state, do
     if ((threadIdx.x & 63) == 0 && bal) atomicAdd(active, __popcll(bal));
 }
 
+// Systems still active when conjugate gradients reached its iteration cap:
+// *count += their number.
+__global__ void k_count_active(int n, const uint8_t *__restrict__ state, int *__restrict__ count) {
+    const int sc = blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned long long bal = __ballot(sc < n && state[sc] == 0);
+    if ((threadIdx.x & 63) == 0 && bal) atomicAdd(count, __popcll(bal));
+}
+
 // Scatter the CG solutions into the dense fits and compute their losses.
 __global__ __launch_bounds__(256) void k_cg_finish(int p, int pe, int R, int nL, int W,
                                                    const uint64_t *__restrict__ supp,
@@ -546,7 +553,7 @@ struct EstimWork {
     double *Fit, *loss, *Lq;
     double *X, *Rv, *P, *AP, *rr, *rr0, *rrn, *pAp;
     uint8_t *state;
-    int *flags;  // [0] bad factor, [1] active count
+    int *flags;  // [0] bad factor, [1] active count, [2] refits CG left unconverged
 };
 EstimWork carve(const EstimProblem &E, int nL, Arena &ar) {
     EstimWork w{};
@@ -566,7 +573,7 @@ EstimWork carve(const EstimProblem &E, int nL, Arena &ar) {
     w.rrn = ar.take<double>(ns);
     w.pAp = ar.take<double>(ns);
     w.state = ar.take<uint8_t>(ns);
-    w.flags = ar.take<int>(2);
+    w.flags = ar.take<int>(3);
     const size_t nsys = (size_t)E.nb * E.R;
     w.sys = ar.take<int2>(nsys);
     w.off = ar.take<size_t>(nsys);
@@ -583,12 +590,13 @@ size_t estim_work_bytes(const EstimProblem &E) {
 }
 
 // sizes: the support sizes when the caller already read them back (saves a
-// host round trip); the device copy is formed here either way.  bad_host
-// (pinned): the singular-refit flag is copied there and the caller checks it
-// after synchronising the stream; without it the check happens here.  dt: where
-// the stage times are recorded (resolved by the caller), else resolved here.
+// host round trip); the device copy is formed here either way.  flags_host
+// (two ints of pinned memory): the singular-refit flag and the number of refits
+// that conjugate gradients left above its tolerance are copied there, and the
+// caller reads them after synchronising the stream.  dt: where the stage times
+// are recorded (resolved by the caller), else resolved here.
 void estimate(hipStream_t s, const EstimProblem &E, void *work, double *beta_out, int32_t *jstar,
-              double *losses_out, float *stage_ms, const std::vector<int32_t> *sizes, int *bad_host,
+              double *losses_out, float *stage_ms, const std::vector<int32_t> *sizes, int *flags_host,
               DeferredTiming *dt) {
     const int W = (E.p + 63) / 64;
     UOI_REQUIRE(W <= 1024, "estimation: p must be <= 65536");
@@ -623,7 +631,7 @@ void estimate(hipStream_t s, const EstimProblem &E, void *work, double *beta_out
         std::copy(lidx.begin(), lidx.end(), pl);
         UOI_HIP(hipMemcpyAsync(w.Lidx, pl, sizeof(int32_t) * nL, hipMemcpyHostToDevice, s));
     }
-    UOI_HIP(hipMemsetAsync(w.flags, 0, 2 * sizeof(int), s));
+    UOI_HIP(hipMemsetAsync(w.flags, 0, 3 * sizeof(int), s));
 
     // stage times: recorded in the caller's deferred record, else resolved here
     DeferredTiming local;
@@ -698,7 +706,7 @@ void estimate(hipStream_t s, const EstimProblem &E, void *work, double *beta_out
         UOI_HIP(hipMemcpyAsync(w.rr0, w.rr, sizeof(double) * ns, hipMemcpyDeviceToDevice, s));
         UOI_LAUNCH_CHECK();
         CgEpi epi{E.supp, w.Lidx, w.state, w.P, w.AP, w.pAp, E.p, nL, W};
-        for (int it = 0; it < kCgMaxIter; ++it) {
+        for (int it = 0; it < E.cg_max_iter; ++it) {
             UOI_DISPATCH_FN(nL, run_bgemm<double, 1, FN>(s, E.nb, E.p, nL, E.GT, w.P, epi));
             hipLaunchKernelGGL(k_cg_update, eg, dim3(256), 0, s, E.p, nL, w.state, w.rr, w.pAp, w.P, w.AP,
                                w.X, w.Rv, w.rrn);
@@ -714,6 +722,10 @@ void estimate(hipStream_t s, const EstimProblem &E, void *work, double *beta_out
             }
             UOI_HIP(hipMemsetAsync(w.flags + 1, 0, sizeof(int), s));
         }
+        // systems that reached the cap above the tolerance are counted (the fit
+        // reports them as not converged); their current iterates are still used
+        hipLaunchKernelGGL(k_count_active, dim3(cdiv(ns, 256)), dim3(256), 0, s, (int)ns, w.state, w.flags + 2);
+        UOI_LAUNCH_CHECK();
         size_t lds2 = sizeof(double) * ((size_t)(E.p + 1) / 2 + 1 + E.p);
         UOI_REQUIRE(lds2 <= 64 * 1024, "estimation: p too large for the CG finish kernel");
         hipLaunchKernelGGL(k_cg_finish, dim3(nL, E.nb), dim3(256), lds2, s, E.p, E.pe, E.R, nL, W,
@@ -736,14 +748,9 @@ void estimate(hipStream_t s, const EstimProblem &E, void *work, double *beta_out
             local.resolve();
         }
     }
-    if (bad_host) {
-        UOI_HIP(hipMemcpyAsync(bad_host, w.flags, sizeof(int), hipMemcpyDeviceToHost, s));
-        return;
-    }
-    int bad = 0;
-    UOI_HIP(hipMemcpyAsync(&bad, w.flags, sizeof(int), hipMemcpyDeviceToHost, s));
-    UOI_HIP(hipStreamSynchronize(s));
-    if (bad) throw Error(UOI_EINVAL, "estimation: a training Gram restricted to a support is singular");
+    // [0] singular-refit flag, [1] refits left unconverged by conjugate gradients
+    UOI_HIP(hipMemcpyAsync(flags_host, w.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+    UOI_HIP(hipMemcpyAsync(flags_host + 1, w.flags + 2, sizeof(int), hipMemcpyDeviceToHost, s));
 }
 
 }  // namespace uoi

@@ -1,7 +1,7 @@
 // Batched inverse M = (G + rho I)^{-1} in float64 for the ADMM x-update.
 //
 // The paper factors (X'X + rho I) once and applies it with triangular solves
-// every iteration (its "triangular solve" routine, Sec. IV-A.1).  Here the
+// every iteration (the triangular-solve routine of its profile, Sec. IV-A.1).  Here the
 // inverse is formed once per bootstrap so that every ADMM iteration becomes a
 // matrix product.  It is computed by the symmetric sweep operator (block
 // Gauss-Jordan): sweeping pivot block K of a symmetric A with Q = A_KK^{-1}

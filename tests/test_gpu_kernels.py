@@ -200,3 +200,52 @@ def test_admm_reports_nonconvergence(api, orc):
     assert res["status"] == api.UOI_ENOCONV
     its = res["iters"].cpu().numpy()
     assert np.any(its < 0)
+
+
+def _three_bootstraps(orc, pr, n):
+    Gs, cs = [], []
+    for k in range(3):
+        G, c = orc.gram(pr.X, pr.y, orc.boot_rows(0, k, n))
+        Gs.append(G)
+        cs.append(c)
+    return np.array(Gs), np.array(cs)
+
+
+@pytest.mark.parametrize("relax", [1.0, 1.6])
+def test_mixed_tight_tolerance_iterations(api, orc, relax):
+    """A tolerance below what the float32 iteration resolves (1e-10): solves park
+    at the float32 floor and the float64 finish converges them, so the mixed
+    path's iteration counts stay close to the float64 path's (the float32 phase
+    does not run on to the iteration cap)."""
+    pr = synth.lasso_random(200, 50, 10, 5, q=16)
+    Gs, cs = _three_bootstraps(orc, pr, 200)
+    kw = dict(kkt_tol=1e-10, max_iter=50000, relax=relax)
+    r64 = api.lasso_solve_batch(cuda(Gs), cuda(cs), pr.lambdas, precision="fp64", **kw)
+    r32 = api.lasso_solve_batch(cuda(Gs), cuda(cs), pr.lambdas, precision="mixed", **kw)
+    assert r64["status"] == 0 and r32["status"] == 0
+    i64 = r64["iters"].cpu().numpy().astype(float)
+    i32 = r32["iters"].cpu().numpy().astype(float)
+    assert i64.min() >= 0 and i32.min() >= 0
+    print(f"relax {relax}: float64 mean {i64.mean():.1f} max {i64.max():.0f}; "
+          f"mixed mean {i32.mean():.1f} max {i32.max():.0f}")
+    assert i32.max() <= 1.5 * i64.max() + 30
+    assert i32.mean() <= 1.3 * i64.mean() + 15
+    z = r32["z"].cpu().numpy()
+    for k in range(3):
+        for j in range(pr.lambdas.size):
+            assert orc.kkt(Gs[k], cs[k], pr.lambdas[j], z[k, j]) <= 1e-8
+
+
+def test_mixed_iteration_cap_bounds_both_phases(api, orc):
+    """max_iter bounds the float32 phase and the float64 finish together: no
+    converged solve reports more than max_iter iterations, the others are flagged."""
+    pr = synth.lasso_random(200, 50, 10, 5, q=16)
+    Gs, cs = _three_bootstraps(orc, pr, 200)
+    cap = 40
+    res = api.lasso_solve_batch(cuda(Gs), cuda(cs), pr.lambdas, kkt_tol=1e-10, max_iter=cap,
+                                precision="mixed")
+    its = res["iters"].cpu().numpy()
+    assert res["status"] == api.UOI_ENOCONV
+    assert np.any(its < 0)
+    assert its.max() <= cap
+    assert np.all((its == -1) | (its >= 0))
