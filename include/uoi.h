@@ -209,6 +209,25 @@ int uoi_lasso_solve_batch(int32_t nb, int32_t p, const double *G, const double *
                           double *z_out, double *u_out, int32_t *iters, double *kkt);
 
 /*
+ * uoi_lasso_solve_batch without any allocation, for callers that cannot
+ * allocate (code under stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc): same arguments, results and errors as
+ * uoi_lasso_solve_batch, computed by the same kernels.  The scratch memory is a
+ * static device array of UOI_NOALLOC_SCRATCH_BYTES (64 MiB) built into the
+ * library, one per device, held until the process ends; the call allocates no
+ * device or pinned host memory and creates no stream or event (the host reads
+ * the convergence counts synchronously).  A problem whose scratch exceeds the
+ * array (about 8*nb*p*p + 48*nb*q*p bytes in float64, more in UOI_MIXED) is
+ * rejected with UOI_EINVAL before any device work.  opts.warm_start must be
+ * UOI_COLD.  Every call on a device shares that device's array: calls that
+ * overlap on one device race and must be serialised by the caller.
+ */
+#define UOI_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int uoi_lasso_solve_batch_noalloc(int32_t nb, int32_t p, const double *G, const double *c,
+                                  const uoi_opts *o, const double *z0, const double *u0,
+                                  double *z_out, double *u_out, int32_t *iters, double *kkt);
+
+/*
  * LASSO solves sharing a Gram: for each of nb Grams G_b, pe linear terms
  * C_b[:, e] (C [nb*p*pe], c[b][i][e]), each at all q lambdas of opts; the
  * solves of one Gram run as one batched ADMM (the structure of the per-equation

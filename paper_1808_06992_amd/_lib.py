@@ -76,7 +76,7 @@ EXPORTS = (
     "uoi_spd_inverse", "uoi_release_workspace", "uoi_last_error", "uoi_version",
     "uoi_mlp_create", "uoi_mlp_destroy", "uoi_mlp_num_params", "uoi_mlp_set_params",
     "uoi_mlp_get_params", "uoi_mlp_forward", "uoi_mlp_loss_grad", "uoi_mlp_train_step",
-    "uoi_ws_dataset", "uoi_lasso_solve_multi",
+    "uoi_ws_dataset", "uoi_lasso_solve_multi", "uoi_lasso_solve_batch_noalloc",
 )
 
 _lib = None
@@ -99,6 +99,8 @@ def load():
     L.uoi_var_fit.argtypes = [i32, i32, i32, P, i32, C.POINTER(Opts), P, P, P, P, C.POINTER(Diag)]
     L.uoi_lasso_solve_batch.restype = i32
     L.uoi_lasso_solve_batch.argtypes = [i32, i32, P, P, C.POINTER(Opts), P, P, P, P, P, P]
+    L.uoi_lasso_solve_batch_noalloc.restype = i32
+    L.uoi_lasso_solve_batch_noalloc.argtypes = [i32, i32, P, P, C.POINTER(Opts), P, P, P, P, P, P]
     L.uoi_gram.restype = i32
     L.uoi_gram.argtypes = [i32, i32, P, i32, P, i32, i32, P, i32, P, P, P]
     L.uoi_bootstrap_rows.restype = i32
@@ -257,8 +259,10 @@ def var_fit(series: torch.Tensor, lambdas, B1: int, B2: int, seed: int = 0, *, b
     return out
 
 
-def lasso_solve_batch(G: torch.Tensor, c: torch.Tensor, lambdas, *, z0=None, u0=None, **kw):
-    """ADMM solves of nb LASSOs (G, c) at all lambdas; returns z, u [nb, q, p], iters, kkt."""
+def lasso_solve_batch(G: torch.Tensor, c: torch.Tensor, lambdas, *, z0=None, u0=None,
+                      no_alloc: bool = False, **kw):
+    """ADMM solves of nb LASSOs (G, c) at all lambdas; returns z, u [nb, q, p], iters, kkt.
+    no_alloc: through uoi_lasso_solve_batch_noalloc (static scratch, no allocation)."""
     L = load()
     G = _dev(G); c = _dev(c)
     nb, p, _ = G.shape
@@ -269,7 +273,7 @@ def lasso_solve_batch(G: torch.Tensor, c: torch.Tensor, lambdas, *, z0=None, u0=
     u = torch.empty((nb, q, p), dtype=torch.float64, device=dev)
     its = torch.empty((nb, q), dtype=torch.int32, device=dev)
     kkt = torch.empty((nb, q), dtype=torch.float64, device=dev)
-    fn = L.uoi_lasso_solve_batch
+    fn = L.uoi_lasso_solve_batch_noalloc if no_alloc else L.uoi_lasso_solve_batch
     code = _check(fn(nb, p, _ptr(G), _ptr(c), C.byref(o),
                      _ptr(None if z0 is None else _dev(z0)),
                      _ptr(None if u0 is None else _dev(u0)),

@@ -111,3 +111,15 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     with pytest.raises(ImportError):
         _lib.load()
 
+
+def test_no_alloc_rejects_oversize_before_device_work(api):
+    """The allocation-free entry point checks the problem's scratch against its
+    static array before touching the device (fake pointers are never used)."""
+    o, keep = api.make_opts([1.0, 0.5], stream=None)
+    fake = C.c_void_p(0x1000)
+    lib = api.load()
+    code = lib.uoi_lasso_solve_batch_noalloc(40, 1000, fake, fake, C.byref(o), None, None, fake,
+                                             None, None, None)
+    assert code == api.UOI_EINVAL
+    msg = lib.uoi_last_error().decode()
+    assert "static buffer" in msg and str(64 << 20) in msg
