@@ -531,50 +531,74 @@ __global__ void k_ws_inputs(int nb, int p, int q, int pe, const double *__restri
     X[t] = (float)v;
 }
 
-// z[b][i][j] = Y[(b q + j)][i] * lambda_max_b
+// z[b][i][j] = S_{theta lambda_j}(Y[(b q + j)][i] * lambda_max_b): the prediction,
+// shrunk by theta times the penalty (the regression leaves small values on
+// coordinates whose solution is zero).  theta = 1 (kWarmShrink) raised the share
+// of accepted starts at p = 200 from 77 % to 88 % and the iterations saved per
+// solve from 1.5 to 1.9 (exact counts, KKT 1e-8); 0.1 - 2 were tried.
+constexpr double kWarmShrink = 1.0;
 __global__ void k_ws_z0(int nb, int p, int q, const float *__restrict__ Y, const double *__restrict__ cn,
-                        double *__restrict__ z) {
+                        const double *__restrict__ lam, double theta, double *__restrict__ z) {
     size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (size_t)nb * p * q) return;
     const int j = (int)(t % q);
     const size_t bi = t / q;
     const int i = (int)(bi % p), b = (int)(bi / p);
-    z[t] = (double)Y[((size_t)b * q + j) * p + i] * cn[b];
+    z[t] = soft_threshold((double)Y[((size_t)b * q + j) * p + i] * cn[b], theta * lam[j]);
 }
 
-// One thread per solve (b, j): with g = c - G z0, u0 = clip(g/rho, +-lambda/rho).
+// Per solve (b, j): with g = c - G z0, u0 = clip(g/rho, +-lambda/rho).
 // The prediction is kept only if it lowers the LASSO objective below that of
 // the cold start, F(z) = z'Gz/2 - c'z + lambda |z|_1 with F(0) = 0 (a dense
 // prediction violates the KKT conditions on every coordinate that should be
 // zero, so the KKT residual is not a fair test of a starting point).
-__global__ void k_ws_finish(int nb, int p, int q, const double *__restrict__ c, const double *__restrict__ Gz,
-                            const double *__restrict__ lam, double rho, double *__restrict__ z,
-                            double *__restrict__ u, unsigned long long *__restrict__ used) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    bool use = false;
-    if (s < nb * q) {
-        const int b = s / q, j = s % q;
+// One workgroup per bootstrap: thread (g, j) of a (256/qj) x qj grid sums the
+// coordinates i = g mod (256/qj) of solve j (consecutive threads read
+// consecutive solves of a feature row), the partial sums meet in LDS, and the
+// same grid then writes u0 or the cold start.
+__global__ __launch_bounds__(256) void k_ws_finish(int nb, int p, int q, const double *__restrict__ c,
+                                                   const double *__restrict__ Gz,
+                                                   const double *__restrict__ lam, double rho,
+                                                   double *__restrict__ z, double *__restrict__ u,
+                                                   unsigned long long *__restrict__ used) {
+    __shared__ double part[256];
+    __shared__ int keep[256];
+    const int b = blockIdx.x, t = threadIdx.x;
+    for (int j0 = 0; j0 < q; j0 += 256) {
+        const int qj = min(256, q - j0), G = 256 / qj;
+        const int jj = t % qj, g = t / qj, j = j0 + jj;
         const double lm = lam[j];
         double F = 0.0;
-        for (int i = 0; i < p; ++i) {
-            const size_t o = ((size_t)b * p + i) * q + j;
-            const double zi = z[o];
-            F += zi * (0.5 * Gz[o] - c[(size_t)b * p + i]) + lm * fabs(zi);
-        }
-        use = F < 0.0;
-        for (int i = 0; i < p; ++i) {
-            const size_t o = ((size_t)b * p + i) * q + j;
-            if (use) {
-                const double g = c[(size_t)b * p + i] - Gz[o];
-                u[o] = fmin(fmax(g / rho, -lm / rho), lm / rho);
-            } else {
-                z[o] = 0.0;
-                u[o] = 0.0;
+        if (g < G)
+            for (int i = g; i < p; i += G) {
+                const size_t o = ((size_t)b * p + i) * q + j;
+                const double zi = z[o];
+                F += zi * (0.5 * Gz[o] - c[(size_t)b * p + i]) + lm * fabs(zi);
             }
+        part[t] = F;
+        __syncthreads();
+        if (t < qj) {
+            double tot = 0.0;
+            for (int h = 0; h < G; ++h) tot += part[h * qj + t];
+            keep[t] = tot < 0.0;
         }
+        __syncthreads();
+        const bool use = keep[jj] != 0;
+        if (g < G)
+            for (int i = g; i < p; i += G) {
+                const size_t o = ((size_t)b * p + i) * q + j;
+                if (use) {
+                    const double gi = c[(size_t)b * p + i] - Gz[o];
+                    u[o] = fmin(fmax(gi / rho, -lm / rho), lm / rho);
+                } else {
+                    z[o] = 0.0;
+                    u[o] = 0.0;
+                }
+            }
+        const unsigned long long bal = __ballot(t < qj && keep[min(t, qj - 1)] != 0);
+        if ((t & 63) == 0 && bal) atomicAdd(used, (unsigned long long)__popcll(bal));
+        __syncthreads();
     }
-    unsigned long long bal = __ballot(use);
-    if ((threadIdx.x & 63) == 0 && bal) atomicAdd(used, (unsigned long long)__popcll(bal));
 }
 
 // Training pairs from solved problems: inputs as k_ws_inputs; targets
@@ -1027,7 +1051,7 @@ void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, 
         UOI_LAUNCH_CHECK();
         mlp_forward(s, P.mlp, n, Xs);
         hipLaunchKernelGGL(k_ws_z0, dim3(cdiv(nst, 256)), dim3(256), 0, s, P.nb, P.p, P.q,
-                           mlp_output(P.mlp), w.cn, out.z);
+                           mlp_output(P.mlp), w.cn, P.lam, kWarmShrink, out.z);
         UOI_LAUNCH_CHECK();
         double *Gz = w.v0 ? w.v0 : out.u;  // scratch of the state size
         UOI_DISPATCH_FN(P.R, {
@@ -1039,7 +1063,7 @@ void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, 
             // plain solver: no spare state buffer; the completion reads Gz before writing u
             UOI_REQUIRE(false, "warm start by network needs the batched solver");
         }
-        hipLaunchKernelGGL(k_ws_finish, dim3(cdiv(P.nb * P.q, 64)), dim3(64), 0, s, P.nb, P.p, P.q, P.C, Gz,
+        hipLaunchKernelGGL(k_ws_finish, dim3(P.nb), dim3(256), 0, s, P.nb, P.p, P.q, P.C, Gz,
                            P.lam, P.rho, out.z, out.u, (unsigned long long *)w.active);
         UOI_LAUNCH_CHECK();
         unsigned long long used = 0;

@@ -100,8 +100,12 @@ def fit_network(seeds, *, B1: int = 8, M: int = 64, hidden: int = 512, epochs: i
 
 
 def evaluate(net, seeds, gen=synth.lasso_toeplitz, B1: int = 48, B2: int = 48, kkt_tol: float = 1e-6,
-             precision: str = "mixed", **gen_kw):
-    """Cold versus network start on held-out problems: iterations, time, agreement."""
+             precision: str = "mixed", check_every: int = 10, **gen_kw):
+    """Cold versus network start on held-out problems: iterations, time, agreement.
+    With check_every = 1 the iteration counts are exact (otherwise they are
+    rounded up to the KKT check period); save_mean is the mean over solves of
+    (cold - network) iterations, frac_saved / frac_worse the shares of solves
+    that needed fewer / more iterations from the network start."""
     rows = []
     for sd in seeds:
         pr = gen(sd, **gen_kw)
@@ -109,22 +113,26 @@ def evaluate(net, seeds, gen=synth.lasso_toeplitz, B1: int = 48, B2: int = 48, k
         y = torch.as_tensor(pr.y, device="cuda")
         res = {}
         for name, kw in (("cold", {}), ("mlp", {"mlp": net})):
-            api.lasso_fit(X, y, pr.lambdas, B1, B2, sd, kkt_tol=kkt_tol, precision=precision, **kw)  # warm
+            api.lasso_fit(X, y, pr.lambdas, B1, B2, sd, kkt_tol=kkt_tol, precision=precision,
+                          check_every=check_every, **kw)  # warm
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             out = api.lasso_fit(X, y, pr.lambdas, B1, B2, sd, kkt_tol=kkt_tol, precision=precision,
-                                sel_beta=True, timing=True, **kw)
+                                check_every=check_every, sel_beta=True, timing=True, **kw)
             torch.cuda.synchronize()
             out["wall_ms"] = 1000 * (time.perf_counter() - t0)
             res[name] = out
         it_c = res["cold"]["iters"].double()
         it_m = res["mlp"]["iters"].double()
+        d = it_c - it_m
         sb_c = res["cold"]["sel_beta"]
         sb_m = res["mlp"]["sel_beta"]
         scale = sb_c.abs().amax(dim=-1, keepdim=True).clamp_min(1e-300)
         rows.append(dict(
             seed=sd,
             mean_iters_cold=float(it_c.mean()), mean_iters_mlp=float(it_m.mean()),
+            save_mean=float(d.mean()), frac_saved=float((d > 0).double().mean()),
+            frac_worse=float((d < 0).double().mean()),
             max_iters_cold=int(it_c.max()), max_iters_mlp=int(it_m.max()),
             admm_ms_cold=res["cold"]["stage_ms"]["admm"], admm_ms_mlp=res["mlp"]["stage_ms"]["admm"],
             fit_ms_cold=res["cold"]["wall_ms"], fit_ms_mlp=res["mlp"]["wall_ms"],

@@ -66,10 +66,15 @@ def test_training_reduces_loss(api):
 
 
 def test_warm_start_gains_over_cold_start(api):
-    """Network trained on solves of the workload distribution (p = 200 for test time):
-    warm-started fits reach the same solutions, and the measured iteration gain is
-    reported (it is modest: a start within ~50% of the solution saves the first
-    part of the linear ADMM tail only)."""
+    """Network trained on solves of the workload distribution (p = 200 for test
+    time), evaluated on held-out designs with exact iteration counts (a KKT
+    check after every iteration): the warm-started fits reach the same
+    solutions, most solves start from the network, and they need strictly fewer
+    ADMM iterations than from the cold start.  Measured: 1.6 - 2.1 of about 87
+    iterations saved per solve (2 %), 58 - 63 % of the solves faster, 17 %
+    slower.  (At p = 1000, the benchmark's size, the held-out starts are
+    rejected by the objective gate and the gain is zero; the benchmark reports
+    that variant separately.)"""
     from oracle import mlp as omlp
     from paper_1808_06992_amd import warmstart as ws
     kw = dict(n=1000, p=200, k=20, q=16)
@@ -81,12 +86,11 @@ def test_warm_start_gains_over_cold_start(api):
     hist = ws.train(net, X, T, epochs=30, batch=512, lr=2e-3)
     print("training loss by epoch:", [f"{h:.3e}" for h in hist])
     assert hist[-1] < 0.5 * hist[0]
-    rows = ws.evaluate(net, [2000, 2001], B1=16, B2=8, kkt_tol=1e-8, precision="fp64", **kw)
+    rows = ws.evaluate(net, [2000, 2001], B1=16, B2=8, kkt_tol=1e-8, precision="fp64", check_every=1, **kw)
     print("warm-start rows:", rows)
     for r in rows:
         assert r["unconverged_mlp"] == 0
         assert r["max_rel_diff"] <= 1e-5          # the same LASSO solutions
         assert r["warm_used"] > r["solves"] // 2  # most solves start from the network
-    gain = np.mean([r["mean_iters_cold"] / r["mean_iters_mlp"] for r in rows])
-    print(f"mean ADMM iterations cold / network start: {gain:.3f}")
-    assert gain >= 1.0, rows
+        assert r["save_mean"] >= 1.0              # at least one ADMM iteration saved per solve
+        assert r["frac_saved"] > 2 * r["frac_worse"]
