@@ -21,7 +21,8 @@ TAG_LASSO_BOOT, TAG_LASSO_SPLIT, TAG_VAR_BOOT, TAG_VAR_SPLIT = 1, 2, 3, 4
 __all__ = [
     "build", "lib", "mix64", "key", "index", "boot_rows", "split_rows", "var_block_len",
     "var_boot_rows", "var_split_rows", "gram", "gram_var", "kkt", "lasso_cd", "lstsq_qr",
-    "ols_normal", "uoi_lasso", "uoi_var", "decided_bits", "support_words",
+    "ols_normal", "uoi_lasso", "uoi_var", "uoi_var_d", "gram_multi", "decided_bits",
+    "support_words",
 ]
 
 
@@ -70,6 +71,9 @@ def lib():
         L.orc_uoi_var.restype = i32
         L.orc_uoi_var.argtypes = [i32, i32, P, i32, i32, i32, i32, P, u64, i32, i32, f64, i32,
                                   P, P, P, P]
+        L.orc_uoi_var_d.restype = i32
+        L.orc_uoi_var_d.argtypes = [i32, i32, i32, i32, P, i32, i32, i32, i32, P, u64, i32, i32, f64,
+                                    i32, P, P, P, P, P]
         _lib = L
     return _lib
 
@@ -154,6 +158,18 @@ def gram_var(series: np.ndarray, rows: np.ndarray):
     G = np.empty((p, p))
     Cm = np.empty((p, p))
     lib().orc_gram(rows.size, _p(rows), p, _p(s), p, p, s[1:].ctypes.data, p, _p(G), _p(Cm))
+    return G, Cm
+
+
+def gram_multi(X: np.ndarray, Y: np.ndarray, rows: np.ndarray):
+    """G = X_r'X_r/m and C = X_r'Y_r/m over the sampled rows, several response columns."""
+    X = _f64(X); Y = _f64(Y)
+    rows = np.ascontiguousarray(rows, np.int32)
+    n, p = X.shape
+    pe = Y.shape[1]
+    G = np.empty((p, p))
+    Cm = np.empty((p, pe))
+    lib().orc_gram(rows.size, _p(rows), p, _p(X), p, pe, _p(Y), pe, _p(G), _p(Cm))
     return G, Cm
 
 
@@ -258,3 +274,22 @@ def uoi_var(series, lambdas, B1, B2, seed, *, block_len=0, num=4, den=5, tol=1e-
     st = lib().orc_uoi_var(T, p, _p(s), block_len, B1, B2, q, _p(lam), seed, num, den, tol,
                            max_sweeps, _p(A), _p(supp), _p(jstar), _p(losses))
     return dict(status=int(st), A=A, supports=supp, jstar=jstar, losses=losses)
+
+
+def uoi_var_d(series, lambdas, B1, B2, seed, *, d=1, intercept=False, block_len=0, num=4, den=5,
+              tol=1e-12, max_sweeps=100000):
+    """Algorithm 2 for VAR(d) (Eq. (5)-(8)), optionally with an unpenalised intercept.
+    A[l, e, m] = coefficient of x_{t-l-1, m} in equation e; mu [p]; supports [q][p][W]
+    with bit l*p + m of equation e (Eq. (7) column order), W = ceil(d*p/64)."""
+    s = _f64(series); lam = _f64(lambdas)
+    T, p = s.shape
+    q = lam.size
+    W = (d * p + 63) // 64
+    A = np.empty((d, p, p))
+    mu = np.empty(p)
+    supp = np.empty((q, p, W), np.uint64)
+    jstar = np.empty(B2, np.int32)
+    losses = np.empty((B2, q))
+    st = lib().orc_uoi_var_d(T, p, d, 1 if intercept else 0, _p(s), block_len, B1, B2, q, _p(lam), seed,
+                             num, den, tol, max_sweeps, _p(A), _p(mu), _p(supp), _p(jstar), _p(losses))
+    return dict(status=int(st), A=A, mu=mu, supports=supp, jstar=jstar, losses=losses)

@@ -584,3 +584,150 @@ int orc_uoi_var(int T, int p, const double *series, int L, int B1, int B2, int q
     free(rows); free(G); free(C); free(tr); free(ev); free(fit); free(Lk); free(acc);
     return bad ? -1 : 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Alg. 2 for a VAR(d) series (Eq. (5)-(8)), with an optional intercept.     */
+/*                                                                            */
+/* Regression row r = 0..N-1 (N = T - d) has the response x_{r+d} and, as in */
+/* Eq. (7), the design [x_{r+d-1}, x_{r+d-2}, ..., x_r] (lag 1 first), built  */
+/* here explicitly as an N x (d p) matrix.  Equation e's coefficient vector  */
+/* b_e (length d p) holds A_l[e][m] at position (l-1) p + m (vec B of Eq. (8) */
+/* stacks these per equation); supports use the same bit positions.          */
+/*                                                                            */
+/* Intercept (Alg. 2 returns mu-hat; Eq. (5) as printed has none): the model */
+/* x_t = mu + sum_l A_l x_{t-l} + u_t with mu unpenalised.  Every sample --   */
+/* each bootstrap sample of the selection, each training set of the          */
+/* estimation -- is centred by its own column means (counting repeated rows  */
+/* with their multiplicity), which profiles mu out of the least-squares term.*/
+/* A refit's intercept is mu_e = ybar_T[e] - xbar_T' b_e, its loss uses the   */
+/* residuals y - mu - x'b on the evaluation rows, and mu-hat averages the     */
+/* chosen refits' intercepts like every other coefficient of beta*.          */
+/* ------------------------------------------------------------------------ */
+
+/* Centred copy of the sampled rows: out row a = src[rows[a]] - mean over the sample. */
+static void centred_sample(int m, const int32_t *rows, int w, const double *src, double *out,
+                           double *mean, int centre)
+{
+    for (int c = 0; c < w; ++c) mean[c] = 0.0;
+    if (centre) {
+        for (int a = 0; a < m; ++a)
+            for (int c = 0; c < w; ++c) mean[c] += src[(size_t)rows[a] * w + c];
+        for (int c = 0; c < w; ++c) mean[c] /= m;
+    }
+    for (int a = 0; a < m; ++a)
+        for (int c = 0; c < w; ++c) out[(size_t)a * w + c] = src[(size_t)rows[a] * w + c] - mean[c];
+}
+
+int orc_uoi_var_d(int T, int p, int d, int intercept, const double *series, int L, int B1, int B2,
+                  int q, const double *lam, uint64_t seed, int num, int den, double tol,
+                  int max_sweeps, double *A_out, double *mu_out, uint64_t *supp, int32_t *jstar,
+                  double *losses)
+{
+    const int N = T - d, P = d * p;
+    const int W = (P + 63) / 64;
+    if (L <= 0) L = orc_var_block_len(N);
+    int bad = 0;
+    /* the lagged design (Eq. (7), lag 1 first) and the responses (Eq. (6)) */
+    double *Xl = (double *)malloc(sizeof(double) * (size_t)N * P);
+    double *Yl = (double *)malloc(sizeof(double) * (size_t)N * p);
+    for (int r = 0; r < N; ++r) {
+        for (int l = 0; l < d; ++l)
+            for (int m = 0; m < p; ++m)
+                Xl[(size_t)r * P + (size_t)l * p + m] = series[(size_t)(r + d - 1 - l) * p + m];
+        for (int e = 0; e < p; ++e) Yl[(size_t)r * p + e] = series[(size_t)(r + d) * p + e];
+    }
+    size_t sw = (size_t)q * p * W;
+    for (size_t t = 0; t < sw; ++t) supp[t] = ~(uint64_t)0;
+    if (P % 64)
+        for (size_t t = 0; t < (size_t)q * p; ++t) supp[t * W + W - 1] = ((uint64_t)1 << (P % 64)) - 1;
+    int32_t *rows = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
+    int32_t *iden = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
+    for (int r = 0; r < N; ++r) iden[r] = r;
+    double *Xs = (double *)malloc(sizeof(double) * (size_t)N * P);
+    double *Ys = (double *)malloc(sizeof(double) * (size_t)N * p);
+    double *xm = (double *)malloc(sizeof(double) * (size_t)P);
+    double *ym = (double *)malloc(sizeof(double) * (size_t)p);
+    double *G = (double *)malloc(sizeof(double) * (size_t)P * P);
+    double *C = (double *)malloc(sizeof(double) * (size_t)P * p);
+    /* Model selection */
+    for (int k = 0; k < B1; ++k) {
+        orc_var_boot_rows(seed, k, N, L, rows);
+        centred_sample(N, rows, P, Xl, Xs, xm, intercept);
+        centred_sample(N, rows, p, Yl, Ys, ym, intercept);
+        orc_gram(N, iden, P, Xs, P, p, Ys, p, G, C);
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : bad)
+        for (int e = 0; e < p; ++e) {
+            double *b = (double *)calloc((size_t)P, sizeof(double));
+            uint64_t *w = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)W);
+            for (int j = 0; j < q; ++j) {
+                if (orc_lasso_cd(P, G, C + e, p, lam[j], tol, max_sweeps, b) < 0) ++bad;
+                set_support(P, b, w);
+                uint64_t *S = supp + ((size_t)j * p + e) * W;
+                for (int t = 0; t < W; ++t) S[t] &= w[t];
+            }
+            free(b); free(w);
+        }
+    }
+    /* Model estimation */
+    int32_t *tr = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
+    int32_t *ev = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
+    double *fit = (double *)malloc(sizeof(double) * (size_t)q * p * P);
+    double *fmu = (double *)malloc(sizeof(double) * (size_t)q * p);
+    double *Lk = (double *)malloc(sizeof(double) * (size_t)q * p);
+    double *acc = (double *)calloc((size_t)p * P, sizeof(double));
+    double *macc = (double *)calloc((size_t)p, sizeof(double));
+    for (int k = 0; k < B2; ++k) {
+        int ntr = 0, nev = 0;
+        orc_var_split_rows(seed, k, N, L, num, den, tr, &ntr, ev, &nev);
+        centred_sample(ntr, tr, P, Xl, Xs, xm, intercept);
+        centred_sample(ntr, tr, p, Yl, Ys, ym, intercept);
+        orc_gram(ntr, iden, P, Xs, P, p, Ys, p, G, C);
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : bad)
+        for (int e = 0; e < p; ++e) {
+            double *work = (double *)malloc(sizeof(double) * (size_t)P * P);
+            double *bs = (double *)malloc(sizeof(double) * (size_t)P);
+            int *idx = (int *)malloc(sizeof(int) * (size_t)P);
+            for (int j = 0; j < q; ++j) {
+                int s = support_list(P, supp + ((size_t)j * p + e) * W, idx);
+                if (orc_ols_normal(P, G, C + e, p, s, idx, bs, work) != 0) ++bad;
+                double *f = fit + ((size_t)j * p + e) * P;
+                memset(f, 0, sizeof(double) * (size_t)P);
+                double mu = ym[e];
+                for (int a = 0; a < s; ++a) {
+                    f[idx[a]] = bs[a];
+                    mu -= xm[idx[a]] * bs[a];
+                }
+                fmu[(size_t)j * p + e] = intercept ? mu : 0.0;
+                double Ls = 0.0;
+                for (int r = 0; r < nev; ++r) {
+                    const double *x = Xl + (size_t)ev[r] * P;
+                    double res = Yl[(size_t)ev[r] * p + e] - fmu[(size_t)j * p + e];
+                    for (int a = 0; a < s; ++a) res -= x[idx[a]] * bs[a];
+                    Ls += res * res;
+                }
+                Lk[(size_t)j * p + e] = nev > 0 ? Ls / nev : 0.0;
+            }
+            free(work); free(bs); free(idx);
+        }
+        int best = 0;
+        double bestL = 0.0;
+        for (int j = 0; j < q; ++j) {
+            double s = 0.0;
+            for (int e = 0; e < p; ++e) s += Lk[(size_t)j * p + e];
+            if (losses) losses[(size_t)k * q + j] = s;
+            if (j == 0 || s < bestL) { bestL = s; best = j; }
+        }
+        jstar[k] = best;
+        for (size_t t = 0; t < (size_t)p * P; ++t) acc[t] += fit[(size_t)best * p * P + t];
+        for (int e = 0; e < p; ++e) macc[e] += fmu[(size_t)best * p + e];
+    }
+    /* A_l[e][m] = beta*_e[(l-1) p + m] (Alg. 2, last steps) */
+    for (int l = 0; l < d; ++l)
+        for (int e = 0; e < p; ++e)
+            for (int m = 0; m < p; ++m)
+                A_out[((size_t)l * p + e) * p + m] = acc[(size_t)e * P + (size_t)l * p + m] / B2;
+    for (int e = 0; e < p; ++e) mu_out[e] = macc[e] / B2;
+    free(Xl); free(Yl); free(rows); free(iden); free(Xs); free(Ys); free(xm); free(ym); free(G);
+    free(C); free(tr); free(ev); free(fit); free(fmu); free(Lk); free(acc); free(macc);
+    return bad ? -1 : 0;
+}

@@ -61,12 +61,15 @@ class LassoProblem:
 @dataclass
 class VarProblem:
     series: np.ndarray     # T x p, float64, time ascending
-    A_true: np.ndarray     # p x p, float64
+    A_true: np.ndarray     # p x p (d = 1) or d x p x p (A_true[l] multiplies x_{t-l-1}), float64
     lambdas: np.ndarray    # q, float64, strictly decreasing
     B1: int
     B2: int
     seed: int
     name: str = ""
+    d: int = 1             # autoregressive order
+    intercept: bool = False
+    mu_true: np.ndarray | None = None
 
 
 def _log_grid(lam_max: float, q: int, ratio: float) -> np.ndarray:
@@ -89,6 +92,61 @@ def lambda_grid_var(series: np.ndarray, q: int, ratio: float = 1e-3) -> np.ndarr
     Yl = series[1:]
     lam_max = float(np.max(np.abs(Xl.T @ Yl))) / Xl.shape[0]
     return _log_grid(lam_max, q, ratio)
+
+
+def lagged_design(series: np.ndarray, d: int):
+    """Eq. (6)-(7): responses x_t (t = d .. T-1) and designs [x_{t-1}, ..., x_{t-d}] (lag 1 first)."""
+    T, p = series.shape
+    N = T - d
+    Xl = np.hstack([series[d - 1 - l: d - 1 - l + N] for l in range(d)])
+    return np.ascontiguousarray(Xl), np.ascontiguousarray(series[d:])
+
+
+def lambda_grid_var_d(series: np.ndarray, d: int, intercept: bool, q: int,
+                      ratio: float = 1e-3) -> np.ndarray:
+    """lambda_max = max_e ||X'Y_e||_inf / N' over the lagged regression of order d,
+    on centred columns when an intercept is fitted."""
+    Xl, Yl = lagged_design(series, d)
+    if intercept:
+        Xl = Xl - Xl.mean(axis=0)
+        Yl = Yl - Yl.mean(axis=0)
+    lam_max = float(np.max(np.abs(Xl.T @ Yl))) / Xl.shape[0]
+    return _log_grid(lam_max, q, ratio)
+
+
+def var_d(p: int, T: int, d: int, frac: float, radius: float, seed: int, *, mu_scale: float = 0.0,
+          intercept: bool = False, burn: int = 500, q: int = 30, B1: int = 30, B2: int = 30,
+          ratio: float = 1e-3) -> VarProblem:
+    """VAR(d): x_t = mu + sum_l A_l x_{t-l} + u_t, u_t ~ N(0, I), x = 0 before the
+    burn-in.  Each A_l has round(frac p^2) nonzeros ~ N(0, 1) at random positions;
+    A_l is then scaled by s^l so that the companion matrix has spectral radius
+    `radius` (which scales every root of the characteristic polynomial by s).
+    mu ~ N(0, mu_scale^2) per coordinate."""
+    rng = np.random.default_rng(seed)
+    nnz = int(round(frac * p * p))
+    A = np.zeros((d, p, p))
+    for l in range(d):
+        pos = rng.choice(p * p, size=nnz, replace=False)
+        A[l].reshape(-1)[pos] = rng.standard_normal(nnz)
+    comp = np.zeros((d * p, d * p))
+    comp[:p, :] = np.hstack(list(A))
+    comp[p:, :-p] = np.eye((d - 1) * p)
+    rad = float(np.max(np.abs(np.linalg.eigvals(comp)))) if nnz else 0.0
+    if rad > 0:
+        for l in range(d):
+            A[l] *= (radius / rad) ** (l + 1)
+    mu = mu_scale * rng.standard_normal(p)
+    U = rng.standard_normal((T + burn, p))
+    xs = np.zeros((T + burn + d, p))
+    for t in range(d, T + burn + d):
+        x = mu + U[t - d]
+        for l in range(d):
+            x = x + A[l] @ xs[t - 1 - l]
+        xs[t] = x
+    series = np.ascontiguousarray(xs[burn + d:])
+    lam = lambda_grid_var_d(series, d, intercept, q, ratio)
+    return VarProblem(series, A, lam, B1, B2, seed, f"var{d}_p{p}_T{T}", d=d, intercept=intercept,
+                      mu_true=mu)
 
 
 def lasso_random(n: int, p: int, k: int, seed: int, *, noise: float = 0.5, q: int = 16,

@@ -402,6 +402,133 @@ def test_var_p1_is_lasso_on_lagged_regression(orc):
         assert a[0] == pytest.approx(_soft(c2[0], lam) / G2[0, 0], abs=1e-14)
 
 
+def _lagged(s, d):
+    """Eq. (6)-(7) written out: responses x_t, designs [x_{t-1}, ..., x_{t-d}] (lag 1 first)."""
+    T, p = s.shape
+    N = T - d
+    Xl = np.zeros((N, d * p))
+    for r in range(N):
+        for l in range(d):
+            Xl[r, l * p:(l + 1) * p] = s[r + d - 1 - l]
+    return Xl, s[d:].copy()
+
+
+def test_var_d1_route_equals_lag_one_route(orc):
+    """The VAR(d) routine (explicit lagged design) at d = 1 without intercept gives
+    exactly what the lag-one routine (strided rows of the series) gives."""
+    pr = synth.var1(5, 300, 0.3, 0.8, 2, burn=50, q=4, B1=3, B2=3)
+    a = orc.uoi_var(pr.series, pr.lambdas, pr.B1, pr.B2, 77)
+    b = orc.uoi_var_d(pr.series, pr.lambdas, pr.B1, pr.B2, 77, d=1)
+    assert a["status"] == 0 and b["status"] == 0
+    assert np.array_equal(a["supports"], b["supports"])
+    assert np.array_equal(a["jstar"], b["jstar"])
+    np.testing.assert_allclose(b["losses"], a["losses"], rtol=1e-12)
+    np.testing.assert_allclose(b["A"][0], a["A"], rtol=1e-12, atol=1e-15)
+    assert np.all(b["mu"] == 0.0)
+
+
+def test_var_d_kronecker_form_equals_per_equation_lasso(orc):
+    """Eq. (8) built literally for VAR(2) at p = 3: the LASSO on vec Y = (I (x) X) vec B,
+    X the lagged design of Eq. (7), splits into one LASSO per equation on X."""
+    pr = synth.var_d(3, 40, 2, 0.5, 0.8, 1, burn=20, q=3)
+    Xl, Yl = _lagged(pr.series, 2)
+    m, P = Xl.shape
+    p = 3
+    K = np.kron(np.eye(p), Xl)                 # (m p) x (p P)
+    vy = Yl.T.reshape(-1)
+    Gk, ck = K.T @ K / m, K.T @ vy / m
+    G, Cm = orc.gram_multi(Xl, Yl, np.arange(m, dtype=np.int32))
+    for lam in pr.lambdas:
+        bk, st = orc.lasso_cd(Gk, ck, lam)
+        assert st >= 0
+        for e in range(p):
+            be, _ = orc.lasso_cd(G, Cm[:, e], lam)
+            np.testing.assert_allclose(bk[e * P:(e + 1) * P], be, rtol=1e-10, atol=1e-13)
+
+
+@pytest.mark.parametrize("d,intercept", [(2, True), (3, False), (1, True)])
+def test_uoi_var_d_composition(orc, d, intercept):
+    """Alg. 2 for VAR(d), recomputed in numpy: the lagged design written out (Eq. (7)),
+    each bootstrap sample centred by its own means when an intercept is fitted,
+    Python-set intersections, and refits by LAPACK least squares with an explicit
+    column of ones for the intercept (no centring algebra) on the training rows."""
+    pr = synth.var_d(5, 300, d, 0.3, 0.8, 2, mu_scale=1.5, intercept=intercept, burn=50, q=4, B1=3, B2=3)
+    s = pr.series
+    T, p = s.shape
+    N, P = T - d, d * p
+    L = orc.var_block_len(N)
+    r = orc.uoi_var_d(s, pr.lambdas, pr.B1, pr.B2, 77, d=d, intercept=intercept)
+    assert r["status"] == 0
+    Xl, Yl = _lagged(s, d)
+    q = pr.lambdas.size
+    inter = [[set(range(P)) for _ in range(p)] for _ in range(q)]
+    for k in range(pr.B1):
+        rows = orc.var_boot_rows(77, k, N, L)
+        Xr, Yr = Xl[rows], Yl[rows]
+        if intercept:
+            Xr, Yr = Xr - Xr.mean(axis=0), Yr - Yr.mean(axis=0)
+        G, Cm = Xr.T @ Xr / N, Xr.T @ Yr / N
+        for e in range(p):
+            for j in range(q):
+                b, _ = orc.lasso_cd(G, Cm[:, e], pr.lambdas[j])
+                inter[j][e] &= set(np.nonzero(b)[0].tolist())
+    for j in range(q):
+        for e in range(p):
+            assert _bits_to_set(r["supports"][j, e], P) == inter[j][e]
+    accA = np.zeros((p, P))
+    accm = np.zeros(p)
+    for k in range(pr.B2):
+        tr, ev = orc.var_split_rows(77, k, N, L)
+        Ls, fits, mus = [], [], []
+        for j in range(q):
+            F = np.zeros((p, P))
+            mu = np.zeros(p)
+            tot = 0.0
+            for e in range(p):
+                S = sorted(inter[j][e])
+                Z = Xl[tr][:, S]
+                if intercept:
+                    Z = np.hstack([np.ones((tr.size, 1)), Z])
+                if Z.shape[1]:
+                    coef = np.linalg.lstsq(Z, Yl[tr, e], rcond=None)[0]
+                    if intercept:
+                        mu[e], coef = coef[0], coef[1:]
+                    F[e, S] = coef
+                res = Yl[ev, e] - mu[e] - Xl[ev] @ F[e]
+                tot += res @ res / ev.size
+            Ls.append(tot)
+            fits.append(F)
+            mus.append(mu)
+        np.testing.assert_allclose(r["losses"][k], Ls, rtol=1e-9)
+        assert r["jstar"][k] == int(np.argmin(Ls))
+        accA += fits[r["jstar"][k]]
+        accm += mus[r["jstar"][k]]
+    Aw = (accA / pr.B2).reshape(p, d, p).transpose(1, 0, 2)   # A[l][e][m] = F[e][l p + m]
+    np.testing.assert_allclose(r["A"], Aw, rtol=1e-9, atol=1e-13)
+    np.testing.assert_allclose(r["mu"], accm / pr.B2, rtol=1e-9, atol=1e-12)
+    if not intercept:
+        assert np.all(r["mu"] == 0.0)
+
+
+def test_var_intercept_translation_invariance(orc):
+    """With an intercept, adding a constant c to every observation leaves every
+    centred sample unchanged: the same supports and A, and mu-hat moves by
+    (I - sum_l A_l) c (each refit's intercept is ybar - xbar' b)."""
+    d = 2
+    pr = synth.var_d(5, 300, d, 0.3, 0.8, 4, mu_scale=1.0, intercept=True, burn=50, q=4, B1=3, B2=3)
+    c = np.linspace(-3.0, 2.0, 5)
+    r1 = orc.uoi_var_d(pr.series, pr.lambdas, pr.B1, pr.B2, 5, d=d, intercept=True)
+    r2 = orc.uoi_var_d(pr.series + c, pr.lambdas, pr.B1, pr.B2, 5, d=d, intercept=True)
+    assert np.array_equal(r1["supports"], r2["supports"])
+    assert np.array_equal(r1["jstar"], r2["jstar"])
+    np.testing.assert_allclose(r2["A"], r1["A"], rtol=1e-8, atol=1e-12)
+    shift = c - sum(r1["A"][l] @ c for l in range(d))
+    np.testing.assert_allclose(r2["mu"], r1["mu"] + shift, rtol=1e-8, atol=1e-10)
+    # and without the intercept the constant does change the fit
+    r3 = orc.uoi_var_d(pr.series + c, pr.lambdas, pr.B1, pr.B2, 5, d=d, intercept=False)
+    assert np.all(r3["mu"] == 0.0) and not np.allclose(r3["A"], r1["A"])
+
+
 # ----------------------------------------------------------------------------
 # Warm-start network oracle
 # ----------------------------------------------------------------------------
