@@ -79,7 +79,8 @@ enum {
 };
 
 /* opts.flags */
-#define UOI_FLAG_TIMING 1u  /* fill uoi_diag.stage_ms with hipEvent stage times */
+#define UOI_FLAG_TIMING 1u     /* fill uoi_diag.stage_ms with hipEvent stage times */
+#define UOI_FLAG_INTERCEPT 2u  /* UoI_VAR: fit the intercept mu of Eq. (5) (see uoi_var_fit) */
 
 /* Opaque warm-start network (see the uoi_mlp_* functions below). */
 typedef struct uoi_mlp uoi_mlp;
@@ -174,19 +175,29 @@ int uoi_lasso_fit(int32_t n, int32_t p, const double *X, const double *y, const 
                   double *beta_out, uint64_t *supp_out, int32_t *jstar_out, uoi_diag *diag);
 
 /*
- * UoI_VAR, Algorithm 2, for a VAR(d) series (Eq. (5)); d = 1 is supported.
- * The lag-1 regression of Eq. (6)-(7) uses rows t = 1..T-1 (response X_t,
- * design X_{t-1}).  The vectorised LASSO of Eq. (8) is solved as p per-equation
- * LASSOs that share the design Gram and one lambda (the Kronecker matrix of
- * Eq. (8) is never formed).
- *   T, p       series length (T >= 3) and dimension (p >= 1); d must be 1
+ * UoI_VAR, Algorithm 2, for a VAR(d) series (Eq. (5)): x_t = mu + sum_{l=1..d} A_l x_{t-l} + u_t.
+ * The regression of Eq. (6)-(7) uses rows t = d..T-1 (response x_t, design
+ * [x_{t-1}, ..., x_{t-d}]).  The vectorised LASSO of Eq. (8) is solved as p
+ * per-equation LASSOs that share the design Gram and one lambda (the Kronecker
+ * matrix of Eq. (8) is never formed).
+ * Intercept (opts.flags & UOI_FLAG_INTERCEPT; Alg. 2 returns mu, which Eq. (5)
+ * as printed omits): mu is unpenalised and always in the model.  Every sample
+ * (bootstrap sample, training set) is centred by its own column means (repeated
+ * rows counted with multiplicity); each refit's intercept is
+ * ybar_T - xbar_T' b, its evaluation loss uses the residuals y - mu - x'b, and
+ * mu-hat averages the chosen refits' intercepts like the coefficients.  Without
+ * the flag mu = 0.  The lambdas are in the centred scaling when the flag is set.
+ *   T, p, d    series length, dimension (p >= 1), order (d >= 1, d*p <= 65536), T >= d + 2
  *   series     T*p row-major, time ascending
  *   block_len  bootstrap block length in regression rows; 0 = smallest L with
- *              L^3 >= T-1
- *   A_out      [p*p] A_1 estimate, A[i][l] = coefficient of x_{t-1,l} in equation i
- *   mu_out     [p]   intercept estimate (the model has none: written as zeros)
- *   supp_out   [q*p*W] supports S_j per equation, W = ceil(p/64)
+ *              L^3 >= T-d
+ *   A_out      [d*p*p] A_l[i][m] at ((l-1)*p + i)*p + m: coefficient of x_{t-l,m} in equation i
+ *   mu_out     [p]   intercept estimate (zeros without UOI_FLAG_INTERCEPT)
+ *   supp_out   [q*p*W] supports S_j per equation, W = ceil(d*p/64); bit (l-1)*p + m is the
+ *              coefficient A_l[i][m] (Eq. (7)'s column order)
  *   jstar_out  [B2]  support index chosen per split (one for all equations)
+ * diag->sel_beta, when given, is [B1][q][p][d*p] with the coefficients of each
+ * solve in the library's internal column order (lag d first, lag 1 last).
  */
 int uoi_var_fit(int32_t T, int32_t p, int32_t d, const double *series, int32_t block_len,
                 const uoi_opts *o, double *A_out, double *mu_out, uint64_t *supp_out,

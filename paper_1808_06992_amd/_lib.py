@@ -21,6 +21,7 @@ UOI_FP64, UOI_MIXED = 0, 1
 UOI_COLD, UOI_MLP = 0, 1
 UOI_SOLVER_BATCHED, UOI_SOLVER_PLAIN = 0, 1
 UOI_FLAG_TIMING = 1
+UOI_FLAG_INTERCEPT = 2
 
 PRECISIONS = {"fp64": UOI_FP64, "mixed": UOI_MIXED}
 SOLVERS = {"batched": UOI_SOLVER_BATCHED, "plain": UOI_SOLVER_PLAIN}
@@ -224,38 +225,43 @@ def lasso_fit(X: torch.Tensor, y: torch.Tensor, lambdas, B1: int, B2: int, seed:
     return out
 
 
-def var_fit(series: torch.Tensor, lambdas, B1: int, B2: int, seed: int = 0, *, block_len: int = 0,
-            diag: bool = True, sel_beta: bool = False, **kw):
-    """UoI_VAR (Alg. 2, d = 1) on a device series; A[i, l] = coefficient of x_{t-1,l} in eq. i."""
+def var_fit(series: torch.Tensor, lambdas, B1: int, B2: int, seed: int = 0, *, d: int = 1,
+            intercept: bool = False, block_len: int = 0, diag: bool = True, sel_beta: bool = False, **kw):
+    """UoI_VAR (Alg. 2) of order d on a device series.  A[l, i, m] = coefficient of
+    x_{t-l-1, m} in equation i (returned as [p, p] when d = 1), mu [p] (zeros unless
+    intercept), supports [q, p, ceil(d p / 64)] with bit l*p + m for A[l, i, m]."""
     L = load()
     series = _dev(series)
     T, p = series.shape
     o, lam = make_opts(lambdas, B1=B1, B2=B2, seed=seed, **kw)
+    if intercept:
+        o.flags |= UOI_FLAG_INTERCEPT
     q = lam.size
-    W = (p + 63) // 64
+    P = d * p
+    W = (P + 63) // 64
     dev = series.device
-    A = torch.empty((p, p), dtype=torch.float64, device=dev)
+    A = torch.empty((d, p, p), dtype=torch.float64, device=dev)
     mu = torch.empty(p, dtype=torch.float64, device=dev)
     supp = torch.empty((q, p, W), dtype=torch.int64, device=dev)
     jstar = torch.empty(B2, dtype=torch.int32, device=dev)
-    out = dict(A=A, mu=mu, supports=supp, jstar=jstar)
-    d = Diag()
+    out = dict(A=A[0] if d == 1 else A, mu=mu, supports=supp, jstar=jstar)
+    dg = Diag()
     if diag:
         out["iters"] = torch.empty((B1, q, p), dtype=torch.int32, device=dev)
         out["kkt"] = torch.empty((B1, q, p), dtype=torch.float64, device=dev)
         out["losses"] = torch.empty((B2, q), dtype=torch.float64, device=dev)
-        d.iters, d.kkt, d.losses = out["iters"].data_ptr(), out["kkt"].data_ptr(), out["losses"].data_ptr()
+        dg.iters, dg.kkt, dg.losses = out["iters"].data_ptr(), out["kkt"].data_ptr(), out["losses"].data_ptr()
         if sel_beta:
-            out["sel_beta"] = torch.empty((B1, q, p, p), dtype=torch.float64, device=dev)
-            d.sel_beta = out["sel_beta"].data_ptr()
-    code = _check(L.uoi_var_fit(T, p, 1, _ptr(series), int(block_len), C.byref(o), _ptr(A), _ptr(mu),
-                                _ptr(supp), _ptr(jstar), C.byref(d)))
+            out["sel_beta"] = torch.empty((B1, q, p, P), dtype=torch.float64, device=dev)
+            dg.sel_beta = out["sel_beta"].data_ptr()
+    code = _check(L.uoi_var_fit(T, p, d, _ptr(series), int(block_len), C.byref(o), _ptr(A), _ptr(mu),
+                                _ptr(supp), _ptr(jstar), C.byref(dg)))
     out["status"] = code
-    out["n_unconverged"] = int(d.n_unconverged)
-    out["n_refit_unconverged"] = int(d.n_refit_unconverged)
-    out["max_iters"] = int(d.max_iters)
-    out["stage_ms"] = dict(zip(STAGES, list(d.stage_ms)))
-    out["kstat"] = kstats(d)
+    out["n_unconverged"] = int(dg.n_unconverged)
+    out["n_refit_unconverged"] = int(dg.n_refit_unconverged)
+    out["max_iters"] = int(dg.max_iters)
+    out["stage_ms"] = dict(zip(STAGES, list(dg.stage_ms)))
+    out["kstat"] = kstats(dg)
     return out
 
 

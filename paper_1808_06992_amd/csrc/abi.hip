@@ -287,6 +287,7 @@ struct Timer {
 static int lasso_fit(int n, int p, const double *X, const double *y, const uoi_opts *o,
                      double *beta_out, uint64_t *supp_out, int32_t *jstar_out, uoi_diag *diag) {
     check_opts(o, true);
+    UOI_REQUIRE((o->flags & UOI_FLAG_INTERCEPT) == 0, "the intercept option applies to UoI_VAR");
     UOI_REQUIRE(n >= 2 && p >= 1, "need n >= 2 and p >= 1");
     UOI_REQUIRE(X && y && beta_out && supp_out && jstar_out, "NULL data or output pointer");
     const int ntr = split_count(n, o->train_num, o->train_den), nev = n - ntr;
@@ -440,121 +441,161 @@ static int lasso_fit(int n, int p, const double *X, const double *y, const uoi_o
 }
 
 // ---------------------------------------------------------------------------
-// UoI_VAR (d = 1)
+// UoI_VAR, order d, optional intercept
 // ---------------------------------------------------------------------------
+// Regression row r = 0 .. N-1 (N = T - d): response x_{r+d}, design the slice
+// series[r .. r+d-1] read in place (row stride p, width P = d p, columns from
+// lag d to lag 1); k_var_reorder maps the result to Eq. (7)'s lag order.
 static int var_fit(int T, int p, int d, const double *series, int block_len, const uoi_opts *o,
                    double *A_out, double *mu_out, uint64_t *supp_out, int32_t *jstar_out, uoi_diag *diag) {
     check_opts(o, true);
-    UOI_REQUIRE(d == 1, "only VAR(1) is supported (d must be 1)");
-    UOI_REQUIRE(T >= 3 && p >= 1, "need T >= 3 and p >= 1");
+    UOI_REQUIRE(d >= 1, "the autoregressive order d must be >= 1");
+    UOI_REQUIRE(p >= 1 && (int64_t)T >= (int64_t)d + 2, "need p >= 1 and T >= d + 2");
     UOI_REQUIRE(series && A_out && mu_out && supp_out && jstar_out, "NULL data or output pointer");
-    const int N = T - 1;
+    UOI_REQUIRE((int64_t)d * p <= 65536, "d * p must be <= 65536");
+    const int N = T - d, P = d * p;
     const int L = block_len > 0 ? block_len : var_block_len_default(N);
-    UOI_REQUIRE(L <= N, "block_len must be <= T-1");
+    UOI_REQUIRE(L <= N, "block_len must be <= T-d");
     const int nblk = (N + L - 1) / L;
     const int nbt = split_count(nblk, o->train_num, o->train_den);
     UOI_REQUIRE(nbt >= 1 && nbt < nblk, "estimation split leaves no training or evaluation block");
     UOI_REQUIRE((int64_t)o->B1 * o->q * p <= (int64_t)1 << 30, "too many solves");
     hipStream_t s = (hipStream_t)o->stream;
     const bool timing = (o->flags & UOI_FLAG_TIMING) != 0;
+    const bool icpt = (o->flags & UOI_FLAG_INTERCEPT) != 0;
     float sm[8] = {0};
     if (diag) std::memset(diag->kstat, 0, sizeof(diag->kstat));
 
     const int B1 = o->B1, B2 = o->B2, q = o->q, pe = p, R = q * p;
+    const int W = (P + 63) / 64;
     UOI_REQUIRE(o->warm_start == UOI_COLD, "warm start by network is for UoI_LASSO only");
-    AdmmProblem P{B1, p, q, pe, R, nullptr, nullptr, nullptr, o->rho, o->kkt_tol, o->max_iter,
-                  o->check_every, nullptr, o->relax};
-    EstimProblem E{B2, p, pe, q, R, nullptr, nullptr, nullptr, nullptr, nullptr, supp_out, o->cg_max_iter};
-    size_t nst = (size_t)B1 * p * R;
-    auto layout = [&](Arena &a, int32_t *&rows, double *&G, double *&C, double *&lam, double *&z,
-                      double *&u, int32_t *&its, double *&kkt, uint8_t *&flag, int32_t *&tr,
-                      int32_t *&ev, int32_t *&ntr, int32_t *&nev, double *&GT, double *&CT,
-                      double *&GE, double *&CE, double *&sE, void *&admm_w, void *&est_w, void *&cw) {
+    AdmmProblem Pb{B1, P, q, pe, R, nullptr, nullptr, nullptr, o->rho, o->kkt_tol, o->max_iter,
+                   o->check_every, nullptr, o->relax};
+    EstimProblem E{B2, P, pe, q, R, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, o->cg_max_iter};
+    const size_t nst = (size_t)B1 * P * R;
+    struct Buf {
+        int32_t *rows, *its, *tr, *ev, *ntr, *nev;
+        double *G, *C, *lam, *z, *u, *kkt, *GT, *CT, *GE, *CE, *sE;
+        double *xS, *yS, *xE, *yE, *xT, *yT, *xA, *yA, *beta;  // means (intercept), beta* (d > 1)
+        uint64_t *supp;                                       // internal-order supports (d > 1)
+        uint8_t *flag;
+        void *admm_w, *est_w, *cw;
+    } bf{};
+    auto layout = [&](Arena &a, Buf &x) {
         // draws, counts, distinct rows, weights, sizes, input check flag
-        rows = a.take<int32_t>((size_t)4 * B1 * N + B1 + 4);
-        G = a.take<double>((size_t)B1 * p * p);
-        C = a.take<double>((size_t)B1 * p * pe);
-        lam = a.take<double>(q);
-        z = a.take<double>(nst);
-        u = a.take<double>(nst);
-        its = a.take<int32_t>((size_t)B1 * R);
-        kkt = a.take<double>((size_t)B1 * R);
-        flag = a.take<uint8_t>((size_t)B2 * nblk);
-        tr = a.take<int32_t>((size_t)B2 * N);
-        ev = a.take<int32_t>((size_t)B2 * N);
-        ntr = a.take<int32_t>(B2);
-        nev = a.take<int32_t>(B2);
-        GT = a.take<double>((size_t)B2 * p * p);
-        CT = a.take<double>((size_t)B2 * p * pe);
-        GE = a.take<double>((size_t)B2 * p * p);
-        CE = a.take<double>((size_t)B2 * p * pe);
-        sE = a.take<double>((size_t)B2 * pe);
-        admm_w = a.take<char>(admm_work_bytes(P, o->precision, o->solver));
-        est_w = a.take<char>(estim_work_bytes(E));
-        cw = a.take<char>(complement_work_bytes(N, p, pe));
+        x.rows = a.take<int32_t>((size_t)4 * B1 * N + B1 + 4);
+        x.G = a.take<double>((size_t)B1 * P * P);
+        x.C = a.take<double>((size_t)B1 * P * pe);
+        x.lam = a.take<double>(q);
+        x.z = a.take<double>(nst);
+        x.u = a.take<double>(nst);
+        x.its = a.take<int32_t>((size_t)B1 * R);
+        x.kkt = a.take<double>((size_t)B1 * R);
+        x.flag = a.take<uint8_t>((size_t)B2 * nblk);
+        x.tr = a.take<int32_t>((size_t)B2 * N);
+        x.ev = a.take<int32_t>((size_t)B2 * N);
+        x.ntr = a.take<int32_t>(B2);
+        x.nev = a.take<int32_t>(B2);
+        x.GT = a.take<double>((size_t)B2 * P * P);
+        x.CT = a.take<double>((size_t)B2 * P * pe);
+        x.GE = a.take<double>((size_t)B2 * P * P);
+        x.CE = a.take<double>((size_t)B2 * P * pe);
+        x.sE = a.take<double>((size_t)B2 * pe);
+        if (icpt) {
+            x.xS = a.take<double>((size_t)B1 * P);
+            x.yS = a.take<double>((size_t)B1 * pe);
+            x.xE = a.take<double>((size_t)B2 * P);
+            x.yE = a.take<double>((size_t)B2 * pe);
+            x.xT = a.take<double>((size_t)B2 * P);
+            x.yT = a.take<double>((size_t)B2 * pe);
+            x.xA = a.take<double>(P);
+            x.yA = a.take<double>(pe);
+        }
+        if (d > 1) {
+            x.beta = a.take<double>((size_t)pe * P);
+            x.supp = a.take<uint64_t>((size_t)q * pe * W);
+        }
+        x.admm_w = a.take<char>(admm_work_bytes(Pb, o->precision, o->solver));
+        x.est_w = a.take<char>(estim_work_bytes(E));
+        x.cw = a.take<char>(complement_work_bytes(N, P, pe));
     };
-    int32_t *rows, *its, *tr, *ev, *ntr, *nev;
-    double *G, *C, *lam, *z, *u, *kkt, *GT, *CT, *GE, *CE, *sE;
-    uint8_t *flag;
-    void *admm_w, *est_w, *cw;
     Arena ar;
-    layout(ar, rows, G, C, lam, z, u, its, kkt, flag, tr, ev, ntr, nev, GT, CT, GE, CE, sE, admm_w, est_w,
-           cw);
+    layout(ar, bf);
     Arena A;
     A.cap = ar.off;
     A.base = (char *)pool_get(ar.off);
-    layout(A, rows, G, C, lam, z, u, its, kkt, flag, tr, ev, ntr, nev, GT, CT, GE, CE, sE, admm_w, est_w,
-           cw);
-    check_finite(s, rows + (size_t)4 * B1 * N + B1, {{series, (size_t)T * p, "series"}});
+    layout(A, bf);
+    uint64_t *supp = d > 1 ? bf.supp : supp_out;    // supports in the internal column order
+    double *beta = d > 1 ? bf.beta : A_out;          // beta* [equation][internal column]
+    E.supp = supp;
+    check_finite(s, bf.rows + (size_t)4 * B1 * N + B1, {{series, (size_t)T * p, "series"}});
 
-    const double *Xd = series, *Yd = series + p;  // regression row r: x = series[r], y = series[r+1]
+    const double *Xd = series, *Yd = series + (size_t)d * p;  // design rows series[r..], responses series[r+d]
     Timer tm(s, timing);
     KernelTimer gram_timer(s, timing && diag ? &diag->kstat[UOI_KSTAT_GRAM] : nullptr);
     tm.mark();
-    UOI_HIP(hipMemcpyAsync(lam, o->lambdas, sizeof(double) * q, hipMemcpyHostToDevice, s));
-    launch_var_boot_rows(s, o->seed, B1, N, L, rows);
+    UOI_HIP(hipMemcpyAsync(bf.lam, o->lambdas, sizeof(double) * q, hipMemcpyHostToDevice, s));
+    launch_var_boot_rows(s, o->seed, B1, N, L, bf.rows);
     // the estimation splits depend on the seed only: drawn on the second stream
     // beside the selection stage
     AuxStream &ax = aux_stream();
     UOI_HIP(hipEventRecord(ax.e0, s));
     UOI_HIP(hipStreamWaitEvent(ax.s, ax.e0, 0));
-    launch_split(ax.s, o->seed, TAG_VAR_SPLIT, B2, nblk, nbt, flag);
-    launch_expand_blocks(ax.s, B2, nblk, N, L, flag, tr, ev, ntr, nev);
+    launch_split(ax.s, o->seed, TAG_VAR_SPLIT, B2, nblk, nbt, bf.flag);
+    launch_expand_blocks(ax.s, B2, nblk, N, L, bf.flag, bf.tr, bf.ev, bf.ntr, bf.nev);
     UOI_HIP(hipEventRecord(ax.e2, ax.s));
     {
         // distinct regression rows of each block-bootstrap sample, weighted by
         // their multiplicities
-        int32_t *cntb = rows + (size_t)B1 * N, *drow = cntb + (size_t)B1 * N, *dw = drow + (size_t)B1 * N;
+        int32_t *cntb = bf.rows + (size_t)B1 * N, *drow = cntb + (size_t)B1 * N, *dw = drow + (size_t)B1 * N;
         int32_t *nd = dw + (size_t)B1 * N;
-        launch_distinct_rows(s, B1, N, N, rows, cntb, drow, dw, nd);
+        launch_distinct_rows(s, B1, N, N, bf.rows, cntb, drow, dw, nd);
         gram_timer.start();
-        launch_gram_f64_weighted(s, B1, N, drow, dw, nd, N, p, Xd, p, pe, Yd, p, G, C);
+        launch_gram_f64_weighted(s, B1, N, drow, dw, nd, N, P, Xd, p, pe, Yd, p, bf.G, bf.C);
         gram_timer.stop();
+        if (icpt) {  // every bootstrap sample centred by its own means
+            launch_colmeans(s, B1, N, drow, dw, nd, N, P, Xd, p, pe, Yd, p, bf.xS, bf.yS);
+            launch_shift_stats(s, B1, P, pe, bf.G, bf.C, nullptr, bf.xS, bf.yS, bf.xS, bf.yS);
+        }
     }
     tm.mark();
-    P.G = G;
-    P.C = C;
-    P.lam = lam;
-    AdmmOut out{z, u, diag && diag->iters ? diag->iters : its, diag && diag->kkt ? diag->kkt : kkt, 0, 0,
-                timing && diag ? diag->kstat : nullptr, 0};
+    Pb.G = bf.G;
+    Pb.C = bf.C;
+    Pb.lam = bf.lam;
+    AdmmOut out{bf.z, bf.u, diag && diag->iters ? diag->iters : bf.its, diag && diag->kkt ? diag->kkt : bf.kkt, 0,
+                0, timing && diag ? diag->kstat : nullptr, 0};
     DeferredTiming dtm;  // stage and kernel times, read after the final synchronisation
     out.dt = &dtm;
-    admm_solve(s, P, o->precision, o->solver, admm_w, false, out, timing ? sm + 1 : nullptr);
+    admm_solve(s, Pb, o->precision, o->solver, bf.admm_w, false, out, timing ? sm + 1 : nullptr);
     tm.mark();
-    launch_support_and(s, B1, p, R, z, supp_out);
+    launch_support_and(s, B1, P, R, bf.z, supp);
     tm.mark();
     UOI_HIP(hipStreamWaitEvent(s, ax.e2, 0));  // the splits
-    launch_gram_f64(s, B2, N, ev, nev, p, Xd, p, pe, Yd, p, GE, CE, nullptr, 1);
-    launch_colsq(s, B2, N, ev, nev, pe, Yd, p, sE);
-    launch_train_from_eval(s, B2, N, p, Xd, p, pe, Yd, p, GE, CE, 0, 0, ntr, nev, GT, CT, cw);
+    launch_gram_f64(s, B2, N, bf.ev, bf.nev, P, Xd, p, pe, Yd, p, bf.GE, bf.CE, nullptr, 1);
+    launch_colsq(s, B2, N, bf.ev, bf.nev, pe, Yd, p, bf.sE);
+    launch_train_from_eval(s, B2, N, P, Xd, p, pe, Yd, p, bf.GE, bf.CE, 0, 0, bf.ntr, bf.nev, bf.GT, bf.CT,
+                           bf.cw);
+    if (icpt) {
+        // training means from the full-data and evaluation means; evaluation
+        // statistics about the training means, training statistics centred
+        launch_colmeans(s, B2, N, bf.ev, nullptr, bf.nev, 0, P, Xd, p, pe, Yd, p, bf.xE, bf.yE);
+        launch_colmeans(s, 1, N, nullptr, nullptr, nullptr, 0, P, Xd, p, pe, Yd, p, bf.xA, bf.yA);
+        launch_train_means(s, B2, P, pe, N, bf.xA, bf.yA, bf.nev, bf.xE, bf.yE, bf.xT, bf.yT);
+        launch_shift_stats(s, B2, P, pe, bf.GE, bf.CE, bf.sE, bf.xE, bf.yE, bf.xT, bf.yT);
+        launch_shift_stats(s, B2, P, pe, bf.GT, bf.CT, nullptr, bf.xT, bf.yT, bf.xT, bf.yT);
+        E.xT = bf.xT;
+        E.yT = bf.yT;
+        E.mu = mu_out;
+    }
     tm.mark();
-    E.GT = GT; E.CT = CT; E.GE = GE; E.CE = CE; E.sE = sE;
+    E.GT = bf.GT; E.CT = bf.CT; E.GE = bf.GE; E.CE = bf.CE; E.sE = bf.sE;
     int *eflags = (int *)pinned_slot(kPinnedFlag, 2 * sizeof(int));
-    estimate(s, E, est_w, A_out, jstar_out, diag ? diag->losses : nullptr, timing ? sm + 6 : nullptr, nullptr,
+    estimate(s, E, bf.est_w, beta, jstar_out, diag ? diag->losses : nullptr, timing ? sm + 6 : nullptr, nullptr,
              eflags, &dtm);
+    if (d > 1) launch_var_reorder(s, q, p, d, supp, supp_out, beta, A_out);
     tm.mark();
-    UOI_HIP(hipMemsetAsync(mu_out, 0, sizeof(double) * p, s));
-    if (diag && diag->sel_beta) transpose(s, B1, p, R, z, diag->sel_beta, true);
+    if (!icpt) UOI_HIP(hipMemsetAsync(mu_out, 0, sizeof(double) * p, s));
+    if (diag && diag->sel_beta) transpose(s, B1, P, R, bf.z, diag->sel_beta, true);
     UOI_HIP(hipStreamSynchronize(s));
     dtm.resolve();
     if (eflags[0]) throw Error(UOI_EINVAL, "estimation: a training Gram restricted to a support is singular");
@@ -566,9 +607,9 @@ static int var_fit(int T, int p, int d, const double *series, int block_len, con
     }
     admm_finish_stats(out);
     if (timing && diag) {
-        const double md = (double)sum_device_ints(s, rows + (size_t)4 * B1 * N, B1);
-        gram_timer.resolve(md * (p + pe) * 8 + (double)B1 * p * (p + pe) * 8,
-                           md * p * (p + 1) + 2.0 * md * p * pe);
+        const double md = (double)sum_device_ints(s, bf.rows + (size_t)4 * B1 * N, B1);
+        gram_timer.resolve(md * (P + pe) * 8 + (double)B1 * P * (P + pe) * 8,
+                           md * P * (P + 1) + 2.0 * md * P * pe);
     }
     if (diag) {
         diag->n_solves = (int64_t)B1 * R;

@@ -375,11 +375,26 @@ struct EstimProblem {
     const double *sE;      // [nb][pe] mean squares of the responses on evaluation rows
     const uint64_t *supp;  // [R][W]
     int cg_max_iter;       // iteration cap of the conjugate-gradient refits
+    // intercept (optional): training means [nb][p], [nb][pe]; mu [pe] receives the
+    // average over splits of the chosen refits' intercepts ybar_T - xbar_T' b
+    const double *xT = nullptr, *yT = nullptr;
+    double *mu = nullptr;
 };
 size_t estim_work_bytes(const EstimProblem &E);
 void estimate(hipStream_t s, const EstimProblem &E, void *work, double *beta_out, int32_t *jstar,
               double *losses_out, float *stage_ms, const std::vector<int32_t> *sizes, int *flags_host,
               DeferredTiming *dt = nullptr);
+
+// lag order and intercept of UoI_VAR (center.hip)
+void launch_colmeans(hipStream_t s, int nb, int m, const int32_t *rows, const int32_t *w,
+                     const int32_t *mcount, int div, int P, const double *X, int ldx, int pe,
+                     const double *Y, int ldy, double *xbar, double *ybar);
+void launch_shift_stats(hipStream_t s, int nb, int P, int pe, double *G, double *C, double *ss,
+                        const double *xm, const double *ym, const double *a, const double *b);
+void launch_train_means(hipStream_t s, int nb, int P, int pe, int N, const double *xA, const double *yA,
+                        const int32_t *nev, const double *xE, const double *yE, double *xT, double *yT);
+void launch_var_reorder(hipStream_t s, int q, int p, int d, const uint64_t *supp_in, uint64_t *supp_out,
+                        const double *beta, double *A);
 
 // finite check of an array; sets *flag (device int) to 1 on NaN/Inf
 void launch_finite_check(hipStream_t s, const double *x, size_t n, int *flag);

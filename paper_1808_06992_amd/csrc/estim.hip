@@ -538,6 +538,27 @@ __global__ void k_average(int nb, int p, int pe, int R, const double *__restrict
     out[t] = s / nb;
 }
 
+// mu[e] = (1/nb) sum_k (yT[k][e] - xT[k]' Fit[k][jstar_k pe + e]): the intercepts of
+// the chosen refits averaged like their coefficients.  One workgroup per equation.
+__global__ __launch_bounds__(256) void k_intercept(int nb, int p, int pe, int R, const double *__restrict__ Fit,
+                                                   const int32_t *__restrict__ jstar,
+                                                   const double *__restrict__ xT,
+                                                   const double *__restrict__ yT, double *__restrict__ mu) {
+    __shared__ double red[4];
+    const int e = blockIdx.x;
+    double acc = 0.0;
+    for (int k = 0; k < nb; ++k) {
+        const double *f = Fit + ((size_t)k * R + (size_t)jstar[k] * pe + e) * p;
+        const double *x = xT + (size_t)k * p;
+        for (int i = threadIdx.x; i < p; i += 256) acc -= x[i] * f[i];
+        if (threadIdx.x == 0) acc += yT[(size_t)k * pe + e];
+    }
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) mu[e] = (red[0] + red[1] + red[2] + red[3]) / nb;
+}
+
 // ---------------------------------------------------------------------------
 namespace {
 size_t mid_scratch_doubles(const EstimProblem &E) {
@@ -737,6 +758,11 @@ void estimate(hipStream_t s, const EstimProblem &E, void *work, double *beta_out
     hipLaunchKernelGGL(k_average, dim3(cdiv((size_t)E.pe * E.p, 256)), dim3(256), 0, s, E.nb, E.p, E.pe,
                        E.R, w.Fit, jstar, beta_out);
     UOI_LAUNCH_CHECK();
+    if (E.mu) {
+        hipLaunchKernelGGL(k_intercept, dim3(E.pe), dim3(256), 0, s, E.nb, E.p, E.pe, E.R, w.Fit, jstar, E.xT,
+                           E.yT, E.mu);
+        UOI_LAUNCH_CHECK();
+    }
     if (losses_out)
         UOI_HIP(hipMemcpyAsync(losses_out, w.Lq, sizeof(double) * E.nb * E.q, hipMemcpyDeviceToDevice, s));
     if (dtm) {

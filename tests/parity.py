@@ -93,50 +93,66 @@ def check_lasso_estimation(orc, X, y, seed, out, ref=None, js_all=True, rtol=1e-
 
 # --------------------------------------------------------------------------- VAR
 
-def var_split_stats(orc, series, seed, k, num=4, den=5):
-    """Training Gram and cross-products of split k (oracle) and its evaluation rows."""
+def lagged(series, d):
+    """Eq. (6)-(7) written out: responses x_t (t = d .. T-1), designs [x_{t-1} .. x_{t-d}]."""
     T, p = series.shape
-    N = T - 1
+    N = T - d
+    Xl = np.hstack([series[d - 1 - l: d - 1 - l + N] for l in range(d)])
+    return np.ascontiguousarray(Xl), np.ascontiguousarray(series[d:])
+
+
+def var_split_stats(orc, series, seed, k, d=1, intercept=False, num=4, den=5):
+    """Training statistics of split k (oracle Gram over the training rows, centred
+    by the training means when an intercept is fitted), the training means and
+    the evaluation rows."""
+    T, p = series.shape
+    N = T - d
     L = orc.var_block_len(N)
     tr, ev = orc.var_split_rows(seed, k, N, L, num, den)
-    G, Cm = orc.gram_var(series, tr)
-    return G, Cm, ev
+    Xl, Yl = lagged(series, d)
+    Xt, Yt = Xl[tr], Yl[tr]
+    xm = Xt.mean(axis=0) if intercept else np.zeros(Xl.shape[1])
+    ym = Yt.mean(axis=0) if intercept else np.zeros(p)
+    G, Cm = orc.gram_multi(Xt - xm, Yt - ym, np.arange(tr.size, dtype=np.int32))
+    return G, Cm, xm, ym, Xl[ev], Yl[ev]
 
 
 def var_refits(orc, series, stats, bits_j):
-    """Per-equation refits of supports bits_j [p][p] from a split's training
-    statistics (normal-equation Cholesky) and the evaluation loss summed over
-    equations.  Returns (A rows [p][p], loss)."""
-    G, Cm, ev = stats
-    p = series.shape[1]
-    A = np.zeros((p, p))
+    """Per-equation refits of supports bits_j [p][d p] (Eq. (7) column order) from a
+    split's training statistics (normal-equation Cholesky), their intercepts
+    ybar_T - xbar_T' b, and the evaluation loss summed over equations.
+    Returns (coefficients [p][d p], intercepts [p], loss)."""
+    G, Cm, xm, ym, Xe, Ye = stats
+    p, P = bits_j.shape
+    F = np.zeros((p, P))
     for e in range(p):
         S = np.flatnonzero(bits_j[e])
         if S.size:
-            A[e, S] = orc.ols_normal(G, Cm[:, e], S)
-    Xe, Ye = series[ev], series[ev + 1]
-    Rm = Ye - Xe @ A.T
-    return A, float(np.sum(Rm * Rm) / ev.size)
+            F[e, S] = orc.ols_normal(G, Cm[:, e], S)
+    mu = ym - F @ xm
+    Rm = Ye - mu - Xe @ F.T
+    return F, mu, float(np.sum(Rm * Rm) / Xe.shape[0])
 
 
-def check_var_estimation(orc, series, seed, out, ref=None, rtol=1e-9):
-    """Losses of supports that differ from the oracle's, chosen supports and A of a
-    GPU UoI_VAR fit, against refits conditional on the GPU's supports."""
+def check_var_estimation(orc, series, seed, out, ref=None, d=1, intercept=False, rtol=1e-9):
+    """Losses of supports that differ from the oracle's, chosen supports, A and mu of
+    a GPU UoI_VAR fit, against refits conditional on the GPU's supports."""
     T, p = series.shape
-    bits = words_to_bool(out["supports"].cpu().numpy(), p)          # [q][p][p]
+    P = d * p
+    bits = words_to_bool(out["supports"].cpu().numpy(), P)          # [q][p][d p]
     js = out["jstar"].cpu().numpy()
     lg = out["losses"].cpu().numpy()
     B2, q = lg.shape
     assert np.array_equal(js, np.argmin(lg, axis=1))
     same = np.zeros(q, bool)
     if ref is not None:
-        same = np.all(bits == words_to_bool(ref["supports"], p), axis=(1, 2))
+        same = np.all(bits == words_to_bool(ref["supports"], P), axis=(1, 2))
     want = np.empty((B2, q))
     fits, stats = {}, {}
 
     def st(k):
         if k not in stats:
-            stats[k] = var_split_stats(orc, series, seed, k)
+            stats[k] = var_split_stats(orc, series, seed, k, d, intercept)
         return stats[k]
 
     for j in range(q):
@@ -145,18 +161,27 @@ def check_var_estimation(orc, series, seed, out, ref=None, rtol=1e-9):
             continue
         for k in range(B2):
             fits[(k, j)] = var_refits(orc, series, st(k), bits[j])
-            want[k, j] = fits[(k, j)][1]
+            want[k, j] = fits[(k, j)][2]
     np.testing.assert_allclose(lg, want, rtol=rtol, atol=0)
     check_jstar(want, np.argmin(want, axis=1), js)
-    acc = np.zeros((p, p))
+    accA = np.zeros((p, P))
+    accm = np.zeros(p)
     for k in range(B2):
         f = fits.get((k, js[k])) or var_refits(orc, series, st(k), bits[js[k]])
-        acc += f[0]
-    Astar = acc / B2
-    A = out["A"].cpu().numpy()
+        accA += f[0]
+        accm += f[1]
+    Astar = (accA / B2).reshape(p, d, p).transpose(1, 0, 2)        # A[l][e][m] = F[e][l p + m]
+    A = out["A"].cpu().numpy().reshape(d, p, p)
     assert rel(A, Astar) <= rtol if np.abs(Astar).max() > 0 else not np.any(A)
+    mu = out["mu"].cpu().numpy()
+    if intercept:
+        np.testing.assert_allclose(mu, accm / B2, rtol=rtol, atol=rtol * max(np.abs(accm).max() / B2, 1.0))
+    else:
+        assert np.all(mu == 0.0)
     if ref is not None and same.all():
         check_jstar(ref["losses"], ref["jstar"], js)
         if np.array_equal(js, ref["jstar"]):
-            assert rel(A, ref["A"]) <= 1e-6
+            assert rel(A, np.asarray(ref["A"]).reshape(d, p, p)) <= 1e-6
+            if intercept:
+                np.testing.assert_allclose(mu, ref["mu"], rtol=1e-6, atol=1e-6 * np.abs(ref["mu"]).max())
     return dict(same=same, bits=bits)

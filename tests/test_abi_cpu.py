@@ -77,12 +77,25 @@ def test_empty_lambda_grid_rejected(api):
     assert code == api.UOI_EINVAL
 
 
-def test_var_order_must_be_one(api):
+def test_var_order_and_length_checked(api):
     o, keep = api.make_opts([1.0], B1=1, B2=1, stream=None)
     fake = C.c_void_p(0x1000)
-    code = api.load().uoi_var_fit(100, 3, 2, fake, 0, C.byref(o), fake, fake, fake, fake, None)
+    lib = api.load()
+    code = lib.uoi_var_fit(100, 3, 0, fake, 0, C.byref(o), fake, fake, fake, fake, None)
     assert code == api.UOI_EINVAL
-    assert "d must be 1" in api.load().uoi_last_error().decode()
+    assert "order d must be >= 1" in lib.uoi_last_error().decode()
+    code = lib.uoi_var_fit(5, 3, 4, fake, 0, C.byref(o), fake, fake, fake, fake, None)
+    assert code == api.UOI_EINVAL
+    assert "T >= d + 2" in lib.uoi_last_error().decode()
+
+
+def test_intercept_flag_is_for_var(api):
+    o, keep = api.make_opts([1.0], B1=1, B2=1, stream=None)
+    o.flags |= api.UOI_FLAG_INTERCEPT
+    fake = C.c_void_p(0x1000)
+    lib = api.load()
+    assert lib.uoi_lasso_fit(10, 3, fake, fake, C.byref(o), fake, fake, fake, None) == api.UOI_EINVAL
+    assert "UoI_VAR" in lib.uoi_last_error().decode()
 
 
 def test_null_pointers_rejected(api):

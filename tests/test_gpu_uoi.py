@@ -170,3 +170,26 @@ def test_refit_cg_cap_reported(api, orc):
     assert capped["n_unconverged"] == 0 and capped["n_refit_unconverged"] > 0
     full = api.lasso_fit(X, y, pr.lambdas, pr.B1, pr.B2, 5, kkt_tol=1e-10)
     assert full["status"] == 0 and full["n_refit_unconverged"] == 0
+
+
+@pytest.mark.parametrize("d,intercept,p,precision", [(2, True, 12, "fp64"), (3, False, 23, "fp64"),
+                                                     (1, True, 12, "mixed"), (2, True, 40, "mixed")])
+def test_uoi_var_order_d_and_intercept(api, orc, d, intercept, p, precision):
+    """VAR(d) with an optional intercept (Eq. (5)-(8), Alg. 2 returning A_1..A_d and
+    mu) against the oracle's explicit lagged design: supports in Eq. (7)'s column
+    order (d = 3, p = 23: 69 coefficients per equation, two words), then losses,
+    j*, A and mu against oracle refits on the GPU's supports."""
+    seed = 6
+    pr = synth.var_d(p, 600, d, 0.15, 0.8, 4, mu_scale=1.0, intercept=intercept, burn=50, q=6, B1=4, B2=4)
+    ref = orc.uoi_var_d(pr.series, pr.lambdas, pr.B1, pr.B2, seed, d=d, intercept=intercept)
+    assert ref["status"] == 0
+    print(f"var d={d} intercept={intercept} p={p} {precision}", flush=True)
+    out = api.var_fit(cuda(pr.series), pr.lambdas, pr.B1, pr.B2, seed, d=d, intercept=intercept,
+                      kkt_tol=1e-10, precision=precision)
+    assert out["status"] == 0 and out["n_unconverged"] == 0
+    P = d * p
+    got = words_to_bool(out["supports"].cpu().numpy(), P)
+    want = words_to_bool(ref["supports"], P)
+    mism = np.argwhere(got != want)
+    assert mism.shape[0] <= 2, f"support mismatches {mism.tolist()}"
+    check_var_estimation(orc, pr.series, seed, out, ref, d=d, intercept=intercept)
