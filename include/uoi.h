@@ -81,6 +81,10 @@ enum {
 /* opts.flags */
 #define UOI_FLAG_TIMING 1u     /* fill uoi_diag.stage_ms with hipEvent stage times */
 #define UOI_FLAG_INTERCEPT 2u  /* UoI_VAR: fit the intercept mu of Eq. (5) (see uoi_var_fit) */
+#define UOI_FLAG_EAGER 4u      /* launch every ADMM iteration on its own; by default each
+                                  chunk of iterations between two KKT checks is recorded
+                                  once as a HIP graph (per distinct set of launch arguments,
+                                  cached per device) and replayed with one launch          */
 
 /* Opaque warm-start network (see the uoi_mlp_* functions below). */
 typedef struct uoi_mlp uoi_mlp;

@@ -22,6 +22,7 @@ UOI_COLD, UOI_MLP = 0, 1
 UOI_SOLVER_BATCHED, UOI_SOLVER_PLAIN = 0, 1
 UOI_FLAG_TIMING = 1
 UOI_FLAG_INTERCEPT = 2
+UOI_FLAG_EAGER = 4
 
 PRECISIONS = {"fp64": UOI_FP64, "mixed": UOI_MIXED}
 SOLVERS = {"batched": UOI_SOLVER_BATCHED, "plain": UOI_SOLVER_PLAIN}
@@ -167,7 +168,7 @@ def _ptr(t):
 def make_opts(lambdas, *, B1=1, B2=1, seed=0, rho=1.0, kkt_tol=1e-6, max_iter=20000,
               check_every=10, train=(4, 5), precision="fp64", solver="batched",
               warm_start="cold", timing=False, stream="current", mlp=None, relax=1.0,
-              cg_max_iter=4000):
+              cg_max_iter=4000, eager=False):
     lam = np.ascontiguousarray(np.asarray(lambdas, dtype=np.float64))
     o = Opts()
     load().uoi_default_opts(C.byref(o))
@@ -180,7 +181,7 @@ def make_opts(lambdas, *, B1=1, B2=1, seed=0, rho=1.0, kkt_tol=1e-6, max_iter=20
     o.precision = PRECISIONS[precision]
     o.solver = SOLVERS[solver]
     o.warm_start = WARM[warm_start]
-    o.flags = UOI_FLAG_TIMING if timing else 0
+    o.flags = (UOI_FLAG_TIMING if timing else 0) | (UOI_FLAG_EAGER if eager else 0)
     o.relax = float(relax)
     o.cg_max_iter = int(cg_max_iter)
     o.stream = _stream() if stream == "current" else C.c_void_p(stream)

@@ -73,6 +73,48 @@ void *pinned_slot(int slot, size_t bytes) {
 int *pinned_ints(size_t n) { return (int *)pinned_slot(kPinnedCounts, sizeof(int) * n); }
 
 namespace {
+struct GraphCache {
+    hipStream_t cs = nullptr;  // capture stream (default priority)
+    std::map<std::string, hipGraphExec_t> exec;
+};
+std::mutex g_graph_mu;
+std::map<int, GraphCache> g_graphs;
+constexpr size_t kGraphCacheMax = 64;
+}  // namespace
+
+void graph_launch(hipStream_t s, const GraphKey &key, const std::function<void(hipStream_t)> &record) {
+    int dev = 0;
+    UOI_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    GraphCache &gc = g_graphs[dev];
+    if (!gc.cs) UOI_HIP(hipStreamCreateWithFlags(&gc.cs, hipStreamNonBlocking));
+    auto it = gc.exec.find(key.bytes);
+    if (it == gc.exec.end()) {
+        if (gc.exec.size() >= kGraphCacheMax) {
+            UOI_HIP(hipDeviceSynchronize());  // no cached graph is still running
+            for (auto &kv : gc.exec) (void)hipGraphExecDestroy(kv.second);
+            gc.exec.clear();
+        }
+        hipGraph_t g = nullptr;
+        UOI_HIP(hipStreamBeginCapture(gc.cs, hipStreamCaptureModeRelaxed));
+        try {
+            record(gc.cs);
+        } catch (...) {
+            (void)hipStreamEndCapture(gc.cs, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        UOI_HIP(hipStreamEndCapture(gc.cs, &g));
+        hipGraphExec_t ex = nullptr;
+        const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        UOI_HIP(e);
+        it = gc.exec.emplace(key.bytes, ex).first;
+    }
+    UOI_HIP(hipGraphLaunch(it->second, s));
+}
+
+namespace {
 std::mutex g_event_mu;
 std::map<int, std::vector<hipEvent_t>> g_events;  // free timing events per device
 }  // namespace
@@ -301,6 +343,7 @@ static int lasso_fit(int n, int p, const double *X, const double *y, const uoi_o
     const int B1 = o->B1, B2 = o->B2, q = o->q, R = q;
     AdmmProblem P{B1, p, q, 1, R, nullptr, nullptr, nullptr, o->rho, o->kkt_tol, o->max_iter,
                   o->check_every, o->warm_start == UOI_MLP ? o->mlp : nullptr, o->relax};
+    P.graphs = (o->flags & UOI_FLAG_EAGER) == 0;
     EstimProblem E{B2, p, 1, q, R, nullptr, nullptr, nullptr, nullptr, nullptr, supp_out, o->cg_max_iter};
     size_t nst = (size_t)B1 * p * R;
     // size the scratch arena
@@ -471,6 +514,7 @@ static int var_fit(int T, int p, int d, const double *series, int block_len, con
     UOI_REQUIRE(o->warm_start == UOI_COLD, "warm start by network is for UoI_LASSO only");
     AdmmProblem Pb{B1, P, q, pe, R, nullptr, nullptr, nullptr, o->rho, o->kkt_tol, o->max_iter,
                    o->check_every, nullptr, o->relax};
+    Pb.graphs = (o->flags & UOI_FLAG_EAGER) == 0;
     EstimProblem E{B2, P, pe, q, R, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, o->cg_max_iter};
     const size_t nst = (size_t)B1 * P * R;
     struct Buf {
@@ -640,6 +684,7 @@ int solve_batch(int nb, int p, const double *G, const double *c, const uoi_opts 
     AdmmProblem P{nb, p, q, 1, R, G, c, nullptr, o->rho, o->kkt_tol, o->max_iter, o->check_every,
                   o->warm_start == UOI_MLP ? o->mlp : nullptr, o->relax};
     P.no_alloc = no_alloc;
+    P.graphs = !no_alloc && (o->flags & UOI_FLAG_EAGER) == 0;  // instantiating a graph allocates
     size_t nst = (size_t)nb * p * R;
     auto layout = [&](Arena &a, double *&lam, double *&z, double *&u, int32_t *&its, double *&kk,
                       void *&w) {
@@ -829,6 +874,7 @@ int uoi_lasso_solve_multi(int32_t nb, int32_t p, int32_t pe, const double *G, co
         const int q = o->q, R = q * pe;
         AdmmProblem P{nb, p, q, pe, R, G, C, nullptr, o->rho, o->kkt_tol, o->max_iter, o->check_every,
                       nullptr, o->relax};
+        P.graphs = (o->flags & UOI_FLAG_EAGER) == 0;
         const size_t nst = (size_t)nb * p * R;
         auto layout = [&](Arena &a, double *&lam, double *&z, double *&u, int32_t *&its, double *&kk,
                           void *&w) {

@@ -901,28 +901,45 @@ static int sweep(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T
     DeferredTiming local;
     DeferredTiming *dt = ks ? (out.dt ? out.dt : &local) : nullptr;
     int itq = it;  // iterations queued so far
-    auto run_chunk = [&](int n) {
-        Pending pc{nullptr, nullptr, 0.0, 0.0, n, false};
-        if (dt) pc.e0 = dt->mark(s);
+    // n iterations starting at iteration parity par (the ping-pong buffers of v
+    // alternate with the iteration's parity; the last one leaves the KKT estimate)
+    auto issue = [&](hipStream_t st, int par, int n) {
         for (int t = 0; t < n; ++t) {
-            T *vin = (itq & 1) ? vb : va;
-            T *vout = (itq & 1) ? va : vb;
+            const int odd = (par + t) & 1;
+            T *vin = odd ? vb : va;
+            T *vout = odd ? va : vb;
             UOI_DISPATCH_FN(P.R, {
                 if constexpr (std::is_same<T, float>::value) {
-                    __bf16 *pin = (itq & 1) ? w.vp1 : w.vp0;
-                    __bf16 *pout = (itq & 1) ? w.vp0 : w.vp1;
+                    __bf16 *pin = odd ? w.vp1 : w.vp0;
+                    __bf16 *pout = odd ? w.vp0 : w.vp1;
                     AdmmEpiBf3<FN> epi{h, z, u, pout, w.state, P.lam, P.p, P.R, P.pe, bf3_ldk(P.p),
                                        (float)P.rho, (float)(1.0 / P.rho), (float)P.relax,
                                        t == n - 1 ? w.vmax : nullptr, w.rmax};
-                    run_bgemm_bf3<FN>(s, P.nb, P.p, P.R, M, pin, epi);
+                    run_bgemm_bf3<FN>(st, P.nb, P.p, P.R, M, pin, epi);
                 } else {
                     AdmmEpi<T, 1, FN> epi{h, z, u, vout, w.state, P.lam, P.p, P.R, P.pe, (T)P.rho,
                                           (T)(1.0 / P.rho), (T)P.relax};
-                    run_bgemm<T, 1, FN>(s, P.nb, P.p, P.R, M, vin, epi);
+                    run_bgemm<T, 1, FN>(st, P.nb, P.p, P.R, M, vin, epi);
                 }
             });
-            ++itq;
         }
+    };
+    auto run_chunk = [&](int n) {
+        Pending pc{nullptr, nullptr, 0.0, 0.0, n, false};
+        if (dt) pc.e0 = dt->mark(s);
+        const int par = itq & 1;
+        if (n > 1 && P.graphs) {
+            // the chunk as one graph launch: recorded once per distinct argument set
+            // (every pointer and scalar the launches take is in the key)
+            GraphKey key;
+            key.add(sizeof(T)).add(par).add(n).add(P.nb).add(P.p).add(P.R).add(P.pe).add(M).add(h).add(z)
+                .add(u).add(va).add(vb).add(w.vp0).add(w.vp1).add(w.state).add(P.lam).add(w.vmax).add(w.rmax)
+                .add(P.rho).add(P.relax);
+            graph_launch(s, key, [&](hipStream_t cs) { issue(cs, par, n); });
+        } else {
+            issue(s, par, n);
+        }
+        itq += n;
         if (dt) pc.e1 = dt->mark(s);
         pend.push_back(pc);
     };

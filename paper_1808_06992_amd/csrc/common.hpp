@@ -4,6 +4,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <functional>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -75,6 +76,22 @@ struct AuxStream {
     hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
 };
 AuxStream &aux_stream();
+
+// Launch sequences replayed as HIP graphs.  graph_launch(s, key, record) launches
+// on s the graph of the sequence that record(cs) enqueues on a capture stream cs;
+// the sequence is recorded and instantiated the first time its key is seen, and
+// the key must determine every argument of every launch in it (pointers,
+// sizes, scalars).  Graphs hold kernel launches only (no memset or copy nodes).
+// The cache is per device, bounded, and cleared when it fills.
+struct GraphKey {
+    std::string bytes;
+    template <class V>
+    GraphKey &add(const V &v) {
+        bytes.append(reinterpret_cast<const char *>(&v), sizeof(V));
+        return *this;
+    }
+};
+void graph_launch(hipStream_t s, const GraphKey &key, const std::function<void(hipStream_t)> &record);
 
 struct Arena {
     char *base = nullptr;
@@ -272,6 +289,7 @@ struct AdmmProblem {
     uoi_mlp *mlp;        // warm start by network (LASSO: pe == 1), or nullptr
     double relax;        // over-relaxation alpha (1 = plain scaled ADMM)
     bool no_alloc = false;  // no pinned memory, events or second stream (host waits instead)
+    bool graphs = false;    // each chunk of ADMM iterations replayed as one captured graph
 };
 
 // Timing events of the current device, reused across calls (an event may be

@@ -249,3 +249,40 @@ def test_mixed_iteration_cap_bounds_both_phases(api, orc):
     assert np.any(its < 0)
     assert its.max() <= cap
     assert np.all((its == -1) | (its >= 0))
+
+
+@pytest.mark.parametrize("precision,relax", [("fp64", 1.0), ("mixed", 1.6)])
+def test_graph_replay_matches_eager_launches(api, orc, precision, relax):
+    """Chunks of ADMM iterations replayed as captured graphs give exactly the
+    results of launching every iteration eagerly: several replays of the cached
+    graphs (within a sweep and across calls), with eager work and
+    synchronisations between them, each compared with the eager result."""
+    pr = synth.lasso_random(400, 130, 10, 5, q=9)
+    Gs, cs = _three_bootstraps(orc, pr, 400)
+    G, c = cuda(Gs), cuda(cs)
+    kw = dict(kkt_tol=1e-10, precision=precision, relax=relax, max_iter=50000)
+    ref = api.lasso_solve_batch(G, c, pr.lambdas, eager=True, **kw)
+    assert ref["status"] == 0
+    pr2 = synth.lasso_random(200, 50, 10, 6, q=5)
+    G2, c2 = _three_bootstraps(orc, pr2, 200)
+    for rep in range(3):
+        got = api.lasso_solve_batch(G, c, pr.lambdas, **kw)
+        torch.cuda.synchronize()
+        for key in ("z", "u", "iters", "kkt"):
+            assert torch.equal(got[key], ref[key]), (rep, key)
+        # eager work of another shape between the replays
+        other = api.lasso_solve_batch(cuda(G2), cuda(c2), pr2.lambdas, eager=True, kkt_tol=1e-8)
+        assert other["status"] == 0
+        torch.cuda.synchronize()
+
+
+def test_graph_replay_whole_fit_matches_eager(api, orc):
+    pr = synth.lasso_small(0)
+    X, y = cuda(pr.X), cuda(pr.y)
+    a = api.lasso_fit(X, y, pr.lambdas, pr.B1, pr.B2, 0, kkt_tol=1e-8, precision="mixed", relax=1.8,
+                      eager=True, sel_beta=True)
+    for rep in range(2):
+        b = api.lasso_fit(X, y, pr.lambdas, pr.B1, pr.B2, 0, kkt_tol=1e-8, precision="mixed", relax=1.8,
+                          sel_beta=True)
+        for key in ("beta", "supports", "jstar", "iters", "kkt", "sel_beta", "losses"):
+            assert torch.equal(a[key], b[key]), (rep, key)
