@@ -85,6 +85,14 @@ enum {
                                   chunk of iterations between two KKT checks is recorded
                                   once as a HIP graph (per distinct set of launch arguments,
                                   cached per device) and replayed with one launch          */
+#define UOI_FLAG_NO_TUNE 8u    /* do not time launch-shape candidates: use the choices
+                                  already recorded (in this process, or read from the file
+                                  named by the environment variable UOI_TUNE_FILE) or the
+                                  defaults.  By default the library's autotuner times, on
+                                  the first call of each problem shape, the candidates of
+                                  the ADMM products' column-tile width and of the factor's
+                                  matrices per pass on the live operands (the candidates
+                                  give identical results) and keeps the fastest           */
 
 /* Opaque warm-start network (see the uoi_mlp_* functions below). */
 typedef struct uoi_mlp uoi_mlp;
@@ -327,6 +335,11 @@ int uoi_ws_dataset(int32_t nb, int32_t p, int32_t q, int32_t pe, const double *c
 
 /* Free the library's scratch pool on the current device. */
 void uoi_release_workspace(void);
+
+/* Forget the launch shapes the autotuner recorded in this process (see
+ * UOI_FLAG_NO_TUNE); the file named by UOI_TUNE_FILE, if any, is read again at
+ * the next use. */
+void uoi_tune_reset(void);
 
 /* Message for the last non-OK status returned in this thread ("" if none). */
 const char *uoi_last_error(void);

@@ -23,6 +23,7 @@ UOI_SOLVER_BATCHED, UOI_SOLVER_PLAIN = 0, 1
 UOI_FLAG_TIMING = 1
 UOI_FLAG_INTERCEPT = 2
 UOI_FLAG_EAGER = 4
+UOI_FLAG_NO_TUNE = 8
 
 PRECISIONS = {"fp64": UOI_FP64, "mixed": UOI_MIXED}
 SOLVERS = {"batched": UOI_SOLVER_BATCHED, "plain": UOI_SOLVER_PLAIN}
@@ -78,7 +79,7 @@ EXPORTS = (
     "uoi_spd_inverse", "uoi_release_workspace", "uoi_last_error", "uoi_version",
     "uoi_mlp_create", "uoi_mlp_destroy", "uoi_mlp_num_params", "uoi_mlp_set_params",
     "uoi_mlp_get_params", "uoi_mlp_forward", "uoi_mlp_loss_grad", "uoi_mlp_train_step",
-    "uoi_ws_dataset", "uoi_lasso_solve_multi", "uoi_lasso_solve_batch_noalloc",
+    "uoi_ws_dataset", "uoi_lasso_solve_multi", "uoi_lasso_solve_batch_noalloc", "uoi_tune_reset",
 )
 
 _lib = None
@@ -117,6 +118,8 @@ def load():
     L.uoi_spd_inverse.argtypes = [i32, i32, P, f64, P, P]
     L.uoi_release_workspace.restype = None
     L.uoi_release_workspace.argtypes = []
+    L.uoi_tune_reset.restype = None
+    L.uoi_tune_reset.argtypes = []
     L.uoi_last_error.restype = C.c_char_p
     L.uoi_last_error.argtypes = []
     L.uoi_version.restype = C.c_char_p
@@ -168,7 +171,7 @@ def _ptr(t):
 def make_opts(lambdas, *, B1=1, B2=1, seed=0, rho=1.0, kkt_tol=1e-6, max_iter=20000,
               check_every=10, train=(4, 5), precision="fp64", solver="batched",
               warm_start="cold", timing=False, stream="current", mlp=None, relax=1.0,
-              cg_max_iter=4000, eager=False):
+              cg_max_iter=4000, eager=False, tune=True):
     lam = np.ascontiguousarray(np.asarray(lambdas, dtype=np.float64))
     o = Opts()
     load().uoi_default_opts(C.byref(o))
@@ -181,7 +184,8 @@ def make_opts(lambdas, *, B1=1, B2=1, seed=0, rho=1.0, kkt_tol=1e-6, max_iter=20
     o.precision = PRECISIONS[precision]
     o.solver = SOLVERS[solver]
     o.warm_start = WARM[warm_start]
-    o.flags = (UOI_FLAG_TIMING if timing else 0) | (UOI_FLAG_EAGER if eager else 0)
+    o.flags = ((UOI_FLAG_TIMING if timing else 0) | (UOI_FLAG_EAGER if eager else 0)
+               | (0 if tune else UOI_FLAG_NO_TUNE))
     o.relax = float(relax)
     o.cg_max_iter = int(cg_max_iter)
     o.stream = _stream() if stream == "current" else C.c_void_p(stream)
@@ -366,6 +370,11 @@ def spd_inverse(G: torch.Tensor, rho: float):
 
 def release_workspace():
     load().uoi_release_workspace()
+
+
+def tune_reset():
+    """Forget the autotuner's recorded launch shapes (UOI_TUNE_FILE is read again)."""
+    load().uoi_tune_reset()
 
 
 def version() -> str:

@@ -344,6 +344,7 @@ static int lasso_fit(int n, int p, const double *X, const double *y, const uoi_o
     AdmmProblem P{B1, p, q, 1, R, nullptr, nullptr, nullptr, o->rho, o->kkt_tol, o->max_iter,
                   o->check_every, o->warm_start == UOI_MLP ? o->mlp : nullptr, o->relax};
     P.graphs = (o->flags & UOI_FLAG_EAGER) == 0;
+    P.tune = (o->flags & UOI_FLAG_NO_TUNE) == 0;
     EstimProblem E{B2, p, 1, q, R, nullptr, nullptr, nullptr, nullptr, nullptr, supp_out, o->cg_max_iter};
     size_t nst = (size_t)B1 * p * R;
     // size the scratch arena
@@ -515,6 +516,7 @@ static int var_fit(int T, int p, int d, const double *series, int block_len, con
     AdmmProblem Pb{B1, P, q, pe, R, nullptr, nullptr, nullptr, o->rho, o->kkt_tol, o->max_iter,
                    o->check_every, nullptr, o->relax};
     Pb.graphs = (o->flags & UOI_FLAG_EAGER) == 0;
+    Pb.tune = (o->flags & UOI_FLAG_NO_TUNE) == 0;
     EstimProblem E{B2, P, pe, q, R, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, o->cg_max_iter};
     const size_t nst = (size_t)B1 * P * R;
     struct Buf {
@@ -685,6 +687,7 @@ int solve_batch(int nb, int p, const double *G, const double *c, const uoi_opts 
                   o->warm_start == UOI_MLP ? o->mlp : nullptr, o->relax};
     P.no_alloc = no_alloc;
     P.graphs = !no_alloc && (o->flags & UOI_FLAG_EAGER) == 0;  // instantiating a graph allocates
+    P.tune = !no_alloc && (o->flags & UOI_FLAG_NO_TUNE) == 0;   // timing candidates creates events
     size_t nst = (size_t)nb * p * R;
     auto layout = [&](Arena &a, double *&lam, double *&z, double *&u, int32_t *&its, double *&kk,
                       void *&w) {
@@ -875,6 +878,7 @@ int uoi_lasso_solve_multi(int32_t nb, int32_t p, int32_t pe, const double *G, co
         AdmmProblem P{nb, p, q, pe, R, G, C, nullptr, o->rho, o->kkt_tol, o->max_iter, o->check_every,
                       nullptr, o->relax};
         P.graphs = (o->flags & UOI_FLAG_EAGER) == 0;
+        P.tune = (o->flags & UOI_FLAG_NO_TUNE) == 0;
         const size_t nst = (size_t)nb * p * R;
         auto layout = [&](Arena &a, double *&lam, double *&z, double *&u, int32_t *&its, double *&kk,
                           void *&w) {
@@ -908,6 +912,13 @@ int uoi_lasso_solve_multi(int32_t nb, int32_t p, int32_t pe, const double *G, co
 void uoi_release_workspace(void) {
     try {
         pool_release();
+    } catch (...) {
+    }
+}
+
+void uoi_tune_reset(void) {
+    try {
+        tune_forget();
     } catch (...) {
     }
 }

@@ -104,8 +104,10 @@ struct AdmmEpi {
                     const int i = i_base + 16 * a + mfma_row(T(0), lk, t);
                     if (i >= p) continue;
                     const size_t o = ((size_t)b * p + i) * R + r;
-                    T x = hv[c][a][t] + rho * (T)acc[a][c][t];
-                    if (relaxed) x = alpha * x + (T(1) - alpha) * zv[c][a][t];
+                    // explicit fused multiply-adds: every instance of the epilogue
+                    // rounds the same way, whatever the compiler's contraction choices
+                    T x = fma(rho, (T)acc[a][c][t], hv[c][a][t]);
+                    if (relaxed) x = fma(alpha, x, (T(1) - alpha) * zv[c][a][t]);
                     const T uo = uv[c][a][t];
                     const T zn = soft_threshold(x + uo, thr[c]);
                     const T un = uo + x - zn;
@@ -185,8 +187,9 @@ struct AdmmEpiBf3 {
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const int i = i4 + t;
-                const float x0 = hv[c][t] + rho * acc[0][c][t];
-                const float x = relaxed ? alpha * x0 + (1.0f - alpha) * zv[c][t] : x0;
+                // explicit fused multiply-adds (the same rounding in every instance)
+                const float x0 = fmaf(rho, acc[0][c][t], hv[c][t]);
+                const float x = relaxed ? fmaf(alpha, x0, (1.0f - alpha) * zv[c][t]) : x0;
                 const float uo = uv[c][t];
                 const float zn = soft_threshold(x + uo, thr[c]);
                 const float un = uo + x - zn;
@@ -829,7 +832,7 @@ static void check_launch(hipStream_t s, const AdmmProblem &P, const AdmmWork &w,
     int *act = w.active + (size_t)parity * (1 + P.nb), *act_next = w.active + (size_t)(parity ^ 1) * (1 + P.nb);
     if (estimate || zero) {
     } else if (std::is_same<T, double>::value) {
-        UOI_DISPATCH_FN(P.R, {
+        UOI_DISPATCH_FN_RT(P.fn64, {
             KktEpi<double, 1, FN> epi{P.C, (const double *)z, w.state, P.lam, w.vmax, P.p, P.R, P.pe,
                                       only_active};
             run_bgemm<double, 1, FN>(s, P.nb, P.p, P.R, P.G, (const double *)z, epi);
@@ -840,7 +843,7 @@ static void check_launch(hipStream_t s, const AdmmProblem &P, const AdmmWork &w,
         hipLaunchKernelGGL(k_f32_to_f64, dim3(cdiv(n, 256)), dim3(256), 0, s, n, (const float *)z,
                            w.v0);
         UOI_LAUNCH_CHECK();
-        UOI_DISPATCH_FN(P.R, {
+        UOI_DISPATCH_FN_RT(P.fn64, {
             KktEpi<double, 1, FN> epi{P.C, w.v0, w.state, P.lam, w.vmax, P.p, P.R, P.pe, only_active};
             run_bgemm<double, 1, FN>(s, P.nb, P.p, P.R, P.G, w.v0, epi);
         });
@@ -903,12 +906,13 @@ static int sweep(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T
     int itq = it;  // iterations queued so far
     // n iterations starting at iteration parity par (the ping-pong buffers of v
     // alternate with the iteration's parity; the last one leaves the KKT estimate)
+    const int fnv = std::is_same<T, float>::value ? P.fn32 : P.fn64;
     auto issue = [&](hipStream_t st, int par, int n) {
         for (int t = 0; t < n; ++t) {
             const int odd = (par + t) & 1;
             T *vin = odd ? vb : va;
             T *vout = odd ? va : vb;
-            UOI_DISPATCH_FN(P.R, {
+            UOI_DISPATCH_FN_RT(fnv, {
                 if constexpr (std::is_same<T, float>::value) {
                     __bf16 *pin = odd ? w.vp1 : w.vp0;
                     __bf16 *pout = odd ? w.vp0 : w.vp1;
@@ -932,7 +936,8 @@ static int sweep(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T
             // the chunk as one graph launch: recorded once per distinct argument set
             // (every pointer and scalar the launches take is in the key)
             GraphKey key;
-            key.add(sizeof(T)).add(par).add(n).add(P.nb).add(P.p).add(P.R).add(P.pe).add(M).add(h).add(z)
+            key.add(sizeof(T)).add(par).add(n).add(P.fn32).add(P.fn64).add(P.nb).add(P.p).add(P.R).add(P.pe)
+                .add(M).add(h).add(z)
                 .add(u).add(va).add(vb).add(w.vp0).add(w.vp1).add(w.state).add(P.lam).add(w.vmax).add(w.rmax)
                 .add(P.rho).add(P.relax);
             graph_launch(s, key, [&](hipStream_t cs) { issue(cs, par, n); });
@@ -1008,8 +1013,10 @@ static int sweep(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T
     return active;
 }
 
-void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, void *work,
+void admm_solve(hipStream_t s, const AdmmProblem &P0, int precision, int solver, void *work,
                 bool warm, AdmmOut &out, float *stage_ms) {
+    AdmmProblem P = P0;  // the launch shapes (fn32, fn64) are filled in below
+    P.fn32 = P.fn64 = default_fn(P.R);
     Arena ar;
     ar.base = (char *)work;
     ar.cap = (size_t)-1;
@@ -1042,7 +1049,26 @@ void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, 
         if (ax) UOI_HIP(hipEventRecord(ax->e1, ax->s));
     }
     // factor: M = (G + rho I)^{-1}, h = M C, and ||c||_inf per equation
-    spd_inverse_f64(s, P.nb, P.p, P.G, P.rho, w.M, spd_work, w.M32);  // M32: mixed only
+    {
+        // matrices per pass of the blocked sweep (1, 2 or 3 passes over the batch):
+        // every matrix is swept the same way whatever the pass, so the candidates
+        // give identical results and the autotuner times them on the live batch
+        const size_t pp = (size_t)P.p * P.p;
+        const int ncand = P.nb >= 16 && P.p > 88 ? 3 : 1;
+        auto run_spd = [&](int c) {
+            const int ch = (P.nb + c) / (c + 1);
+            for (int b0 = 0; b0 < P.nb; b0 += ch)
+                spd_inverse_f64(s, std::min(ch, P.nb - b0), P.p, P.G + b0 * pp, P.rho, w.M + b0 * pp, spd_work,
+                                w.M32 ? w.M32 + b0 * pp : nullptr);  // M32: mixed only
+        };
+        const std::string key = "spd_passes/nb" + std::to_string(P.nb) + "/p" + std::to_string(P.p);
+        if (P.tune && ncand > 1) {
+            const TuneResult r = tune_choose(s, key, ncand, run_spd, 1);
+            if (!r.ran_all) run_spd(r.choice);
+        } else {
+            run_spd(ncand > 1 ? std::min(tune_lookup(key, 0), ncand - 1) : 0);
+        }
+    }
     launch_matmul_f64(s, P.nb, P.p, P.pe, w.M, P.C, w.h);
     launch_cnorm(s, P.nb, P.p, P.pe, P.C, w.cn);
     if (dt) ev[1] = dt->mark(s);
@@ -1092,6 +1118,48 @@ void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, 
         UOI_HIP(hipMemsetAsync(out.z, 0, sizeof(double) * nst, s));
         UOI_HIP(hipMemsetAsync(out.u, 0, sizeof(double) * nst, s));
     }
+    // Column-tile width of the batched products (16 FN solves per workgroup).
+    // Candidates: every width except one that needs as many column tiles as a
+    // narrower width with more padding columns (same tiles, more wasted work):
+    // FN = 1, 2, 3 at R = 48, all four at R = 5760 (the VAR fits).  Fewer tiles
+    // re-read M less often, more tiles give more workgroups; the tuner decides.  The
+    // accumulation order of every output, and the epilogue's rounding (explicit
+    // fused multiply-adds), are the same for every width, so the autotuner times
+    // them on the live operands: the float32 iteration with its real epilogue
+    // writing a scratch copy of the state, the float64 one as the bare product.
+    auto pick_fn = [&](bool f32) -> int {
+        std::vector<int> cand;
+        for (int f = 1; f <= 4; ++f) {
+            const long tf = cdiv(P.R, 16 * f), wf = tf * 16 * f - P.R;
+            bool dominated = false;
+            for (int g = 1; g < f; ++g) {
+                const long tg = cdiv(P.R, 16 * g), wg = tg * 16 * g - P.R;
+                if (tg == tf && wg < wf) dominated = true;
+            }
+            if (!dominated) cand.push_back(f);
+        }
+        const std::string key = std::string(f32 ? "admm32_fn" : "admm64_fn") + "/nb" + std::to_string(P.nb) +
+                                "/p" + std::to_string(P.p) + "/R" + std::to_string(P.R);
+        const int nc = (int)cand.size();
+        if (!P.tune || nc == 1) return cand[std::min(std::max(tune_lookup(key, 0), 0), nc - 1)];
+        const size_t nst_ = (size_t)P.nb * P.p * P.R;
+        const TuneResult r = tune_choose(s, key, nc, [&](int c) {
+            UOI_DISPATCH_FN_RT(cand[c], {
+                if (f32) {
+                    // scratch state: z and u in the (idle) float64 buffer, v into the
+                    // plane buffer the first iteration overwrites anyway
+                    float *zs = (float *)w.v0, *us = (float *)w.v0 + nst_;
+                    AdmmEpiBf3<FN> e{w.h32, zs, us, w.vp1, w.state, P.lam, P.p, P.R, P.pe, bf3_ldk(P.p),
+                                     (float)P.rho, (float)(1.0 / P.rho), (float)P.relax, nullptr, w.rmax};
+                    run_bgemm_bf3<FN>(s, P.nb, P.p, P.R, w.M32, w.vp0, e);
+                } else {
+                    StoreEpi<double, 1, FN> e{w.v1, P.p, P.R};
+                    run_bgemm<double, 1, FN>(s, P.nb, P.p, P.R, w.M, out.z, e);
+                }
+            });
+        }, 5);
+        return cand[r.choice];
+    };
     int it = 0, active = 0;
     if (solver == UOI_SOLVER_PLAIN) {
         size_t lds = sizeof(double) * 3 * (size_t)P.p;
@@ -1127,6 +1195,7 @@ void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, 
             k.launches += 1;
         }
     } else if (precision == UOI_FP64) {
+        P.fn64 = pick_fn(false);  // (its scratch output is overwritten by the refresh below)
         hipLaunchKernelGGL(k_refresh_v<double>, dim3(cdiv(nst, 256)), dim3(256), 0, s, nst, out.z,
                            out.u, w.v0, w.v1);
         UOI_LAUNCH_CHECK();
@@ -1156,6 +1225,7 @@ void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, 
             UOI_HIP(hipMemsetAsync(w.u32, 0, sizeof(float) * nst, s));
         }
         UOI_LAUNCH_CHECK();
+        P.fn32 = pick_fn(true);
         // max_iter bounds the two phases together: the float32 phase may take at
         // most half of it (solves still active then go on in float64), and the
         // float64 finish runs up to max_iter on the shared iteration counter, so
@@ -1169,6 +1239,7 @@ void admm_solve(hipStream_t s, const AdmmProblem &P, int precision, int solver, 
         // widen the state and finish parked / active solves in float64
         hipLaunchKernelGGL(k_f32_to_f64, dim3(cdiv(nst, 256)), dim3(256), 0, s, nst, w.z32, out.z);
         hipLaunchKernelGGL(k_f32_to_f64, dim3(cdiv(nst, 256)), dim3(256), 0, s, nst, w.u32, out.u);
+        P.fn64 = pick_fn(false);
         hipLaunchKernelGGL(k_unpark, dim3(cdiv(ns, 256)), dim3(256), 0, s, (size_t)ns, w.state);
         hipLaunchKernelGGL(k_refresh_v<double>, dim3(cdiv(nst, 256)), dim3(256), 0, s, nst, out.z,
                            out.u, w.v0, w.v1);

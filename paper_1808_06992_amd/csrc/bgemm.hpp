@@ -323,6 +323,18 @@ inline void run_bgemm_bf3(hipStream_t s, int nb, int p, int R, const float *A, c
     UOI_LAUNCH_CHECK();
 }
 
+// Column-block width chosen at run time (1..4 blocks of 16 columns).
+#define UOI_DISPATCH_FN_RT(fnv, ...)                               \
+    do {                                                          \
+        switch (fnv) {                                            \
+        case 1: { constexpr int FN = 1; __VA_ARGS__; break; }     \
+        case 2: { constexpr int FN = 2; __VA_ARGS__; break; }     \
+        case 3: { constexpr int FN = 3; __VA_ARGS__; break; }     \
+        default: { constexpr int FN = 4; __VA_ARGS__; break; }    \
+        }                                                         \
+    } while (0)
+inline int default_fn(int R) { return R <= 16 ? 1 : R <= 32 ? 2 : R <= 48 ? 3 : 4; }
+
 // Column-block width: the smallest multiple of 16 that covers R, up to 64.
 #define UOI_DISPATCH_FN(R, ...)                                   \
     do {                                                          \

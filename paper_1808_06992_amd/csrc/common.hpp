@@ -93,6 +93,16 @@ struct GraphKey {
 };
 void graph_launch(hipStream_t s, const GraphKey &key, const std::function<void(hipStream_t)> &record);
 
+// Autotuner of launch shapes whose candidates give identical results (tune.hip).
+struct TuneResult {
+    int choice;    // index of the fastest candidate
+    bool ran_all;  // every candidate was just run on the live problem (outputs in place)
+};
+TuneResult tune_choose(hipStream_t s, const std::string &key, int ncand, const std::function<void(int)> &run,
+                       int reps);
+int tune_lookup(const std::string &key, int fallback);  // recorded choice, or fallback
+void tune_forget();                                     // drop every recorded choice
+
 struct Arena {
     char *base = nullptr;
     size_t off = 0, cap = 0;
@@ -290,6 +300,8 @@ struct AdmmProblem {
     double relax;        // over-relaxation alpha (1 = plain scaled ADMM)
     bool no_alloc = false;  // no pinned memory, events or second stream (host waits instead)
     bool graphs = false;    // each chunk of ADMM iterations replayed as one captured graph
+    bool tune = false;      // pick launch shapes with the autotuner (else recorded or default)
+    int fn32 = 0, fn64 = 0; // column-tile widths of the products (set by admm_solve)
 };
 
 // Timing events of the current device, reused across calls (an event may be

@@ -1,0 +1,107 @@
+// Autotuner for launch shapes whose candidates compute identical results (they
+// differ only in how the work is cut into workgroups or passes, never in the
+// order of any floating-point accumulation), so a candidate can be timed on the
+// live problem and its output kept.
+//
+// tune_choose(s, key, n, run): if key has a recorded choice, returns it (the
+// caller then runs that candidate itself, ran_all = false).  Otherwise runs
+// run(c) for every candidate c on stream s between two events, waits, keeps the
+// fastest, and returns it with ran_all = true: the outputs of the last run are
+// in place, so the caller need not run again.  Choices are kept per device for
+// the process and, when the environment variable UOI_TUNE_FILE names a file,
+// read from it at the first use and appended to it for every new key (one
+// "key choice" line each), so later processes reuse them.
+#include <cstdlib>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+
+#include "common.hpp"
+
+namespace uoi {
+
+namespace {
+std::mutex g_tune_mu;
+std::map<int, std::map<std::string, int>> g_tune;  // device -> key -> choice
+bool g_tune_loaded = false;
+
+const char *tune_file() {
+    const char *f = std::getenv("UOI_TUNE_FILE");
+    return f && *f ? f : nullptr;
+}
+
+void load_file_locked(int dev) {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *f = tune_file();
+    if (!f) return;
+    std::ifstream in(f);
+    std::string line;
+    while (std::getline(in, line)) {
+        std::istringstream ls(line);
+        std::string key;
+        int c = -1;
+        if (ls >> key >> c && c >= 0) g_tune[dev][key] = c;
+    }
+}
+}  // namespace
+
+TuneResult tune_choose(hipStream_t s, const std::string &key, int ncand, const std::function<void(int)> &run,
+                       int reps) {
+    int dev = 0;
+    UOI_HIP(hipGetDevice(&dev));
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        load_file_locked(dev);
+        auto it = g_tune[dev].find(key);
+        if (it != g_tune[dev].end() && it->second < ncand) return TuneResult{it->second, false};
+    }
+    if (ncand <= 1) {
+        if (ncand == 1) run(0);
+        return TuneResult{0, ncand == 1};
+    }
+    std::vector<hipEvent_t> ev(2 * ncand);
+    for (auto &e : ev) UOI_HIP(hipEventCreate(&e));
+    for (int c = 0; c < ncand; ++c) {
+        UOI_HIP(hipEventRecord(ev[2 * c], s));
+        for (int r = 0; r < reps; ++r) run(c);
+        UOI_HIP(hipEventRecord(ev[2 * c + 1], s));
+    }
+    UOI_HIP(hipEventSynchronize(ev[2 * ncand - 1]));
+    int best = 0;
+    float best_ms = 0.f;
+    for (int c = 0; c < ncand; ++c) {
+        float ms = 0.f;
+        UOI_HIP(hipEventElapsedTime(&ms, ev[2 * c], ev[2 * c + 1]));
+        if (c == 0 || ms < best_ms) {
+            best = c;
+            best_ms = ms;
+        }
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[dev][key] = best;
+    if (const char *f = tune_file()) {
+        std::ofstream out(f, std::ios::app);
+        out << key << " " << best << "\n";
+    }
+    return TuneResult{best, true};
+}
+
+int tune_lookup(const std::string &key, int fallback) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fallback;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_file_locked(dev);
+    auto it = g_tune[dev].find(key);
+    return it == g_tune[dev].end() ? fallback : it->second;
+}
+
+void tune_forget() {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
+    g_tune_loaded = false;
+}
+
+}  // namespace uoi

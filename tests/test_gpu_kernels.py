@@ -286,3 +286,53 @@ def test_graph_replay_whole_fit_matches_eager(api, orc):
                           sel_beta=True)
         for key in ("beta", "supports", "jstar", "iters", "kkt", "sel_beta", "losses"):
             assert torch.equal(a[key], b[key]), (rep, key)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_autotuner_candidates_give_identical_results(api, orc, precision, tmp_path, monkeypatch):
+    """Every candidate launch shape the autotuner chooses among -- column-tile width
+    FN = 1..4 of the ADMM products (all four are candidates at R = q pe = 192
+    solves per Gram) and 1..3 passes of the factor over the batch of 16 Grams --
+    gives exactly the default's results: each is forced through a tune file and
+    compared.  Then the tuner times the candidates itself and records its choices."""
+    n, p, nb, pe, q = 400, 130, 16, 16, 12
+    rng = np.random.default_rng(7)
+    X = rng.standard_normal((n, p))
+    B = np.zeros((p, pe))
+    for e in range(pe):
+        B[rng.choice(p, 8, replace=False), e] = rng.uniform(-2, 2, 8)
+    Y = X @ B + 0.5 * rng.standard_normal((n, pe))
+    Gs, Cs = [], []
+    for k in range(nb):
+        G, Cm = orc.gram_multi(X, Y, orc.boot_rows(0, k, n))
+        Gs.append(G)
+        Cs.append(Cm)
+    G, Cm = cuda(np.array(Gs)), cuda(np.array(Cs))
+    lam = np.abs(X.T @ Y).max() / n * np.logspace(0, -2.5, q)
+    path = tmp_path / "tune.txt"
+    path.write_text("")
+    monkeypatch.setenv("UOI_TUNE_FILE", str(path))
+    kw = dict(kkt_tol=1e-9, precision=precision, relax=1.6)
+    api.tune_reset()
+    ref = api.lasso_solve_multi(G, Cm, lam, tune=False, **kw)   # defaults (empty file)
+    assert ref["status"] == 0
+    R = q * pe
+    keys = [f"admm64_fn/nb{nb}/p{p}/R{R}", f"admm32_fn/nb{nb}/p{p}/R{R}", f"spd_passes/nb{nb}/p{p}"]
+    for fn in range(4):
+        for passes in range(3):
+            path.write_text(f"{keys[0]} {fn}\n{keys[1]} {fn}\n{keys[2]} {passes}\n")
+            api.tune_reset()
+            got = api.lasso_solve_multi(G, Cm, lam, tune=False, **kw)
+            for key in ("z", "iters", "kkt"):
+                assert torch.equal(got[key], ref[key]), (fn, passes, key)
+    path.write_text("")
+    api.tune_reset()
+    tuned = api.lasso_solve_multi(G, Cm, lam, **kw)
+    for key in ("z", "iters", "kkt"):
+        assert torch.equal(tuned[key], ref[key]), key
+    rec = dict(line.split() for line in path.read_text().splitlines())
+    assert 0 <= int(rec[keys[2]]) <= 2 and 0 <= int(rec[keys[0]]) <= 3
+    if precision == "mixed":
+        assert 0 <= int(rec[keys[1]]) <= 3
+    monkeypatch.delenv("UOI_TUNE_FILE")
+    api.tune_reset()
