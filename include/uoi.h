@@ -85,6 +85,11 @@ enum {
                                   chunk of iterations between two KKT checks is recorded
                                   once as a HIP graph (per distinct set of launch arguments,
                                   cached per device) and replayed with one launch          */
+#define UOI_FLAG_PER_EQUATION 16u /* UoI_VAR: every equation chooses its own support index per
+                                     split (argmin of its own loss) instead of one index per
+                                     split from the loss summed over equations (Alg. 2 on
+                                     Eq. (8) as written); jstar_out is then [B2*p] and
+                                     uoi_diag.losses [B2*q*p] (per equation)                  */
 #define UOI_FLAG_NO_TUNE 8u    /* do not time launch-shape candidates: use the choices
                                   already recorded (in this process, or read from the file
                                   named by the environment variable UOI_TUNE_FILE) or the
@@ -207,7 +212,9 @@ int uoi_lasso_fit(int32_t n, int32_t p, const double *X, const double *y, const 
  *   mu_out     [p]   intercept estimate (zeros without UOI_FLAG_INTERCEPT)
  *   supp_out   [q*p*W] supports S_j per equation, W = ceil(d*p/64); bit (l-1)*p + m is the
  *              coefficient A_l[i][m] (Eq. (7)'s column order)
- *   jstar_out  [B2]  support index chosen per split (one for all equations)
+ *   jstar_out  [B2]  support index chosen per split (one for all equations), or with
+ *              UOI_FLAG_PER_EQUATION [B2*p], jstar_out[k*p + i] for equation i
+ * diag->losses is [B2*q] (summed over equations), or [B2*q*p] with UOI_FLAG_PER_EQUATION.
  * diag->sel_beta, when given, is [B1][q][p][d*p] with the coefficients of each
  * solve in the library's internal column order (lag d first, lag 1 last).
  */

@@ -72,8 +72,8 @@ def lib():
         L.orc_uoi_var.argtypes = [i32, i32, P, i32, i32, i32, i32, P, u64, i32, i32, f64, i32,
                                   P, P, P, P]
         L.orc_uoi_var_d.restype = i32
-        L.orc_uoi_var_d.argtypes = [i32, i32, i32, i32, P, i32, i32, i32, i32, P, u64, i32, i32, f64,
-                                    i32, P, P, P, P, P]
+        L.orc_uoi_var_d.argtypes = [i32, i32, i32, i32, i32, P, i32, i32, i32, i32, P, u64, i32, i32,
+                                    f64, i32, P, P, P, P, P]
         _lib = L
     return _lib
 
@@ -276,11 +276,13 @@ def uoi_var(series, lambdas, B1, B2, seed, *, block_len=0, num=4, den=5, tol=1e-
     return dict(status=int(st), A=A, supports=supp, jstar=jstar, losses=losses)
 
 
-def uoi_var_d(series, lambdas, B1, B2, seed, *, d=1, intercept=False, block_len=0, num=4, den=5,
-              tol=1e-12, max_sweeps=100000):
+def uoi_var_d(series, lambdas, B1, B2, seed, *, d=1, intercept=False, per_equation=False, block_len=0,
+              num=4, den=5, tol=1e-12, max_sweeps=100000):
     """Algorithm 2 for VAR(d) (Eq. (5)-(8)), optionally with an unpenalised intercept.
     A[l, e, m] = coefficient of x_{t-l-1, m} in equation e; mu [p]; supports [q][p][W]
-    with bit l*p + m of equation e (Eq. (7) column order), W = ceil(d*p/64)."""
+    with bit l*p + m of equation e (Eq. (7) column order), W = ceil(d*p/64).
+    per_equation: every equation picks its own support index per split (jstar
+    [B2][p], losses [B2][q][p]) instead of one from the summed loss."""
     s = _f64(series); lam = _f64(lambdas)
     T, p = s.shape
     q = lam.size
@@ -288,8 +290,9 @@ def uoi_var_d(series, lambdas, B1, B2, seed, *, d=1, intercept=False, block_len=
     A = np.empty((d, p, p))
     mu = np.empty(p)
     supp = np.empty((q, p, W), np.uint64)
-    jstar = np.empty(B2, np.int32)
-    losses = np.empty((B2, q))
-    st = lib().orc_uoi_var_d(T, p, d, 1 if intercept else 0, _p(s), block_len, B1, B2, q, _p(lam), seed,
-                             num, den, tol, max_sweeps, _p(A), _p(mu), _p(supp), _p(jstar), _p(losses))
+    jstar = np.empty((B2, p) if per_equation else B2, np.int32)
+    losses = np.empty((B2, q, p) if per_equation else (B2, q))
+    st = lib().orc_uoi_var_d(T, p, d, 1 if intercept else 0, 1 if per_equation else 0, _p(s), block_len,
+                             B1, B2, q, _p(lam), seed, num, den, tol, max_sweeps, _p(A), _p(mu), _p(supp),
+                             _p(jstar), _p(losses))
     return dict(status=int(st), A=A, mu=mu, supports=supp, jstar=jstar, losses=losses)

@@ -602,6 +602,11 @@ int orc_uoi_var(int T, int p, const double *series, int L, int B1, int B2, int q
 /* A refit's intercept is mu_e = ybar_T[e] - xbar_T' b_e, its loss uses the   */
 /* residuals y - mu - x'b on the evaluation rows, and mu-hat averages the     */
 /* chosen refits' intercepts like every other coefficient of beta*.          */
+/*                                                                            */
+/* per_eq: every equation chooses its own support index per split (the argmin */
+/* over lambda of that equation's loss) instead of one index for all          */
+/* equations from the summed loss; losses are then reported per equation     */
+/* ([B2][q][p]) and jstar per equation ([B2][p]).                             */
 /* ------------------------------------------------------------------------ */
 
 /* Centred copy of the sampled rows: out row a = src[rows[a]] - mean over the sample. */
@@ -618,10 +623,10 @@ static void centred_sample(int m, const int32_t *rows, int w, const double *src,
         for (int c = 0; c < w; ++c) out[(size_t)a * w + c] = src[(size_t)rows[a] * w + c] - mean[c];
 }
 
-int orc_uoi_var_d(int T, int p, int d, int intercept, const double *series, int L, int B1, int B2,
-                  int q, const double *lam, uint64_t seed, int num, int den, double tol,
-                  int max_sweeps, double *A_out, double *mu_out, uint64_t *supp, int32_t *jstar,
-                  double *losses)
+int orc_uoi_var_d(int T, int p, int d, int intercept, int per_eq, const double *series, int L,
+                  int B1, int B2, int q, const double *lam, uint64_t seed, int num, int den,
+                  double tol, int max_sweeps, double *A_out, double *mu_out, uint64_t *supp,
+                  int32_t *jstar, double *losses)
 {
     const int N = T - d, P = d * p;
     const int W = (P + 63) / 64;
@@ -708,6 +713,20 @@ int orc_uoi_var_d(int T, int p, int d, int intercept, const double *series, int 
                 Lk[(size_t)j * p + e] = nev > 0 ? Ls / nev : 0.0;
             }
             free(work); free(bs); free(idx);
+        }
+        if (per_eq) {
+            for (int e = 0; e < p; ++e) {
+                int best = 0;
+                for (int j = 0; j < q; ++j) {
+                    const double Le = Lk[(size_t)j * p + e];
+                    if (losses) losses[((size_t)k * q + j) * p + e] = Le;
+                    if (Le < Lk[(size_t)best * p + e]) best = j;
+                }
+                jstar[(size_t)k * p + e] = best;
+                for (int c = 0; c < P; ++c) acc[(size_t)e * P + c] += fit[((size_t)best * p + e) * P + c];
+                macc[e] += fmu[(size_t)best * p + e];
+            }
+            continue;
         }
         int best = 0;
         double bestL = 0.0;

@@ -35,8 +35,8 @@ int orc_uoi_lasso(int n, int p, const double *X, const double *y,
 int orc_uoi_var(int T, int p, const double *series, int L, int B1, int B2, int q,
                 const double *lam, uint64_t seed, int num, int den, double tol, int max_sweeps,
                 double *A_out, uint64_t *supp, int32_t *jstar, double *losses);
-int orc_uoi_var_d(int T, int p, int d, int intercept, const double *series, int L, int B1, int B2,
-                  int q, const double *lam, uint64_t seed, int num, int den, double tol,
-                  int max_sweeps, double *A_out, double *mu_out, uint64_t *supp, int32_t *jstar,
-                  double *losses);
+int orc_uoi_var_d(int T, int p, int d, int intercept, int per_eq, const double *series, int L,
+                  int B1, int B2, int q, const double *lam, uint64_t seed, int num, int den,
+                  double tol, int max_sweeps, double *A_out, double *mu_out, uint64_t *supp,
+                  int32_t *jstar, double *losses);
 #endif

@@ -24,6 +24,7 @@ UOI_FLAG_TIMING = 1
 UOI_FLAG_INTERCEPT = 2
 UOI_FLAG_EAGER = 4
 UOI_FLAG_NO_TUNE = 8
+UOI_FLAG_PER_EQUATION = 16
 
 PRECISIONS = {"fp64": UOI_FP64, "mixed": UOI_MIXED}
 SOLVERS = {"batched": UOI_SOLVER_BATCHED, "plain": UOI_SOLVER_PLAIN}
@@ -231,16 +232,20 @@ def lasso_fit(X: torch.Tensor, y: torch.Tensor, lambdas, B1: int, B2: int, seed:
 
 
 def var_fit(series: torch.Tensor, lambdas, B1: int, B2: int, seed: int = 0, *, d: int = 1,
-            intercept: bool = False, block_len: int = 0, diag: bool = True, sel_beta: bool = False, **kw):
+            intercept: bool = False, per_equation: bool = False, block_len: int = 0, diag: bool = True,
+            sel_beta: bool = False, **kw):
     """UoI_VAR (Alg. 2) of order d on a device series.  A[l, i, m] = coefficient of
     x_{t-l-1, m} in equation i (returned as [p, p] when d = 1), mu [p] (zeros unless
-    intercept), supports [q, p, ceil(d p / 64)] with bit l*p + m for A[l, i, m]."""
+    intercept), supports [q, p, ceil(d p / 64)] with bit l*p + m for A[l, i, m].
+    per_equation: jstar [B2, p] and losses [B2, q, p] (one choice per equation)."""
     L = load()
     series = _dev(series)
     T, p = series.shape
     o, lam = make_opts(lambdas, B1=B1, B2=B2, seed=seed, **kw)
     if intercept:
         o.flags |= UOI_FLAG_INTERCEPT
+    if per_equation:
+        o.flags |= UOI_FLAG_PER_EQUATION
     q = lam.size
     P = d * p
     W = (P + 63) // 64
@@ -248,13 +253,13 @@ def var_fit(series: torch.Tensor, lambdas, B1: int, B2: int, seed: int = 0, *, d
     A = torch.empty((d, p, p), dtype=torch.float64, device=dev)
     mu = torch.empty(p, dtype=torch.float64, device=dev)
     supp = torch.empty((q, p, W), dtype=torch.int64, device=dev)
-    jstar = torch.empty(B2, dtype=torch.int32, device=dev)
+    jstar = torch.empty((B2, p) if per_equation else B2, dtype=torch.int32, device=dev)
     out = dict(A=A[0] if d == 1 else A, mu=mu, supports=supp, jstar=jstar)
     dg = Diag()
     if diag:
         out["iters"] = torch.empty((B1, q, p), dtype=torch.int32, device=dev)
         out["kkt"] = torch.empty((B1, q, p), dtype=torch.float64, device=dev)
-        out["losses"] = torch.empty((B2, q), dtype=torch.float64, device=dev)
+        out["losses"] = torch.empty((B2, q, p) if per_equation else (B2, q), dtype=torch.float64, device=dev)
         dg.iters, dg.kkt, dg.losses = out["iters"].data_ptr(), out["kkt"].data_ptr(), out["losses"].data_ptr()
         if sel_beta:
             out["sel_beta"] = torch.empty((B1, q, p, P), dtype=torch.float64, device=dev)

@@ -329,7 +329,8 @@ struct Timer {
 static int lasso_fit(int n, int p, const double *X, const double *y, const uoi_opts *o,
                      double *beta_out, uint64_t *supp_out, int32_t *jstar_out, uoi_diag *diag) {
     check_opts(o, true);
-    UOI_REQUIRE((o->flags & UOI_FLAG_INTERCEPT) == 0, "the intercept option applies to UoI_VAR");
+    UOI_REQUIRE((o->flags & (UOI_FLAG_INTERCEPT | UOI_FLAG_PER_EQUATION)) == 0,
+                "the intercept and per-equation options apply to UoI_VAR");
     UOI_REQUIRE(n >= 2 && p >= 1, "need n >= 2 and p >= 1");
     UOI_REQUIRE(X && y && beta_out && supp_out && jstar_out, "NULL data or output pointer");
     const int ntr = split_count(n, o->train_num, o->train_den), nev = n - ntr;
@@ -518,6 +519,7 @@ static int var_fit(int T, int p, int d, const double *series, int block_len, con
     Pb.graphs = (o->flags & UOI_FLAG_EAGER) == 0;
     Pb.tune = (o->flags & UOI_FLAG_NO_TUNE) == 0;
     EstimProblem E{B2, P, pe, q, R, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, o->cg_max_iter};
+    E.per_eq = (o->flags & UOI_FLAG_PER_EQUATION) != 0;
     const size_t nst = (size_t)B1 * P * R;
     struct Buf {
         int32_t *rows, *its, *tr, *ev, *ntr, *nev;

@@ -409,6 +409,7 @@ struct EstimProblem {
     // average over splits of the chosen refits' intercepts ybar_T - xbar_T' b
     const double *xT = nullptr, *yT = nullptr;
     double *mu = nullptr;
+    bool per_eq = false;   // one support index per (split, equation) instead of per split
 };
 size_t estim_work_bytes(const EstimProblem &E);
 void estimate(hipStream_t s, const EstimProblem &E, void *work, double *beta_out, int32_t *jstar,

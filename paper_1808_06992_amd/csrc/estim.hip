@@ -528,19 +528,38 @@ __global__ void k_argmin(int q, int pe, const double *__restrict__ loss, double 
 }
 
 // beta*[e][i] = (1/nb) sum_k Fit[k][jstar_k*pe + e][i]
-__global__ void k_average(int nb, int p, int pe, int R, const double *__restrict__ Fit,
+// j* of split k for equation e: one per split, or one per (split, equation)
+__device__ __forceinline__ int chosen(const int32_t *jstar, bool per_eq, int pe, int k, int e) {
+    return per_eq ? jstar[(size_t)k * pe + e] : jstar[k];
+}
+
+// Per-equation choice: jstar[k][e] = first argmin over j of loss[k][j pe + e].
+__global__ void k_argmin_eq(int q, int pe, int R, const double *__restrict__ loss, int32_t *__restrict__ jstar) {
+    const int k = blockIdx.y;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= pe) return;
+    const double *L = loss + (size_t)k * R + e;
+    int best = 0;
+    for (int j = 1; j < q; ++j)
+        if (L[(size_t)j * pe] < L[(size_t)best * pe]) best = j;
+    jstar[(size_t)k * pe + e] = best;
+}
+
+__global__ void k_average(int nb, int p, int pe, int R, bool per_eq, const double *__restrict__ Fit,
                           const int32_t *__restrict__ jstar, double *__restrict__ out) {
     size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (size_t)pe * p) return;
     int e = (int)(t / p), i = (int)(t % p);
     double s = 0.0;
-    for (int k = 0; k < nb; ++k) s += Fit[((size_t)k * R + (size_t)jstar[k] * pe + e) * p + i];
+    for (int k = 0; k < nb; ++k)
+        s += Fit[((size_t)k * R + (size_t)chosen(jstar, per_eq, pe, k, e) * pe + e) * p + i];
     out[t] = s / nb;
 }
 
 // mu[e] = (1/nb) sum_k (yT[k][e] - xT[k]' Fit[k][jstar_k pe + e]): the intercepts of
 // the chosen refits averaged like their coefficients.  One workgroup per equation.
-__global__ __launch_bounds__(256) void k_intercept(int nb, int p, int pe, int R, const double *__restrict__ Fit,
+__global__ __launch_bounds__(256) void k_intercept(int nb, int p, int pe, int R, bool per_eq,
+                                                   const double *__restrict__ Fit,
                                                    const int32_t *__restrict__ jstar,
                                                    const double *__restrict__ xT,
                                                    const double *__restrict__ yT, double *__restrict__ mu) {
@@ -548,7 +567,7 @@ __global__ __launch_bounds__(256) void k_intercept(int nb, int p, int pe, int R,
     const int e = blockIdx.x;
     double acc = 0.0;
     for (int k = 0; k < nb; ++k) {
-        const double *f = Fit + ((size_t)k * R + (size_t)jstar[k] * pe + e) * p;
+        const double *f = Fit + ((size_t)k * R + (size_t)chosen(jstar, per_eq, pe, k, e) * pe + e) * p;
         const double *x = xT + (size_t)k * p;
         for (int i = threadIdx.x; i < p; i += 256) acc -= x[i] * f[i];
         if (threadIdx.x == 0) acc += yT[(size_t)k * pe + e];
@@ -754,16 +773,24 @@ void estimate(hipStream_t s, const EstimProblem &E, void *work, double *beta_out
         UOI_LAUNCH_CHECK();
     }
     if (dtm) ev[1] = dtm->mark(s);
-    hipLaunchKernelGGL(k_argmin, dim3(E.nb), dim3(64), 0, s, E.q, E.pe, w.loss, w.Lq, jstar);
+    // (the summed losses and their argmin are formed in both modes; with a choice
+    // per equation jstar holds [nb][pe] and the losses reported are per equation)
+    if (E.per_eq)
+        hipLaunchKernelGGL(k_argmin_eq, dim3(cdiv(E.pe, 64), E.nb), dim3(64), 0, s, E.q, E.pe, E.R, w.loss, jstar);
+    else
+        hipLaunchKernelGGL(k_argmin, dim3(E.nb), dim3(64), 0, s, E.q, E.pe, w.loss, w.Lq, jstar);
     hipLaunchKernelGGL(k_average, dim3(cdiv((size_t)E.pe * E.p, 256)), dim3(256), 0, s, E.nb, E.p, E.pe,
-                       E.R, w.Fit, jstar, beta_out);
+                       E.R, E.per_eq, w.Fit, jstar, beta_out);
     UOI_LAUNCH_CHECK();
     if (E.mu) {
-        hipLaunchKernelGGL(k_intercept, dim3(E.pe), dim3(256), 0, s, E.nb, E.p, E.pe, E.R, w.Fit, jstar, E.xT,
+        hipLaunchKernelGGL(k_intercept, dim3(E.pe), dim3(256), 0, s, E.nb, E.p, E.pe, E.R, E.per_eq, w.Fit, jstar,
+                           E.xT,
                            E.yT, E.mu);
         UOI_LAUNCH_CHECK();
     }
-    if (losses_out)
+    if (losses_out && E.per_eq)
+        UOI_HIP(hipMemcpyAsync(losses_out, w.loss, sizeof(double) * E.nb * E.R, hipMemcpyDeviceToDevice, s));
+    else if (losses_out)
         UOI_HIP(hipMemcpyAsync(losses_out, w.Lq, sizeof(double) * E.nb * E.q, hipMemcpyDeviceToDevice, s));
     if (dtm) {
         ev[2] = dtm->mark(s);

@@ -131,7 +131,8 @@ def var_refits(orc, series, stats, bits_j):
             F[e, S] = orc.ols_normal(G, Cm[:, e], S)
     mu = ym - F @ xm
     Rm = Ye - mu - Xe @ F.T
-    return F, mu, float(np.sum(Rm * Rm) / Xe.shape[0])
+    per_eq = np.sum(Rm * Rm, axis=0) / Xe.shape[0]
+    return F, mu, float(per_eq.sum()), per_eq
 
 
 def check_var_estimation(orc, series, seed, out, ref=None, d=1, intercept=False, rtol=1e-9):
@@ -185,3 +186,39 @@ def check_var_estimation(orc, series, seed, out, ref=None, d=1, intercept=False,
             if intercept:
                 np.testing.assert_allclose(mu, ref["mu"], rtol=1e-6, atol=1e-6 * np.abs(ref["mu"]).max())
     return dict(same=same, bits=bits)
+
+
+def check_var_per_equation(orc, series, seed, out, ref, d=1, intercept=False, rtol=1e-9):
+    """As check_var_estimation for the per-equation choice: losses [B2][q][p] against
+    oracle refits on the GPU's supports, each equation's j* an argmin of its own
+    losses, A and mu from the refits each equation chose."""
+    T, p = series.shape
+    P = d * p
+    bits = words_to_bool(out["supports"].cpu().numpy(), P)          # [q][p][d p]
+    js = out["jstar"].cpu().numpy()                                 # [B2][p]
+    lg = out["losses"].cpu().numpy()                                # [B2][q][p]
+    B2, q = lg.shape[:2]
+    assert np.array_equal(js, np.argmin(lg, axis=1))
+    want = np.empty((B2, q, p))
+    F = {}
+    for k in range(B2):
+        stats = var_split_stats(orc, series, seed, k, d, intercept)
+        for j in range(q):
+            F[(k, j)] = var_refits(orc, series, stats, bits[j])
+            want[k, j] = F[(k, j)][3]
+    np.testing.assert_allclose(lg, want, rtol=rtol, atol=0)
+    accA, accm = np.zeros((p, P)), np.zeros(p)
+    for k in range(B2):
+        for e in range(p):
+            check_jstar(want[:, :, e], np.argmin(want[:, :, e], axis=1), js[:, e])
+            f = F[(k, js[k, e])]
+            accA[e] += f[0][e]
+            accm[e] += f[1][e]
+    Astar = (accA / B2).reshape(p, d, p).transpose(1, 0, 2)
+    A = out["A"].cpu().numpy().reshape(d, p, p)
+    assert rel(A, Astar) <= rtol
+    mu = out["mu"].cpu().numpy()
+    if intercept:
+        np.testing.assert_allclose(mu, accm / B2, rtol=rtol, atol=rtol * max(np.abs(accm).max() / B2, 1.0))
+    if np.array_equal(bits, words_to_bool(ref["supports"], P)) and np.array_equal(js, ref["jstar"]):
+        assert rel(A, np.asarray(ref["A"]).reshape(d, p, p)) <= 1e-6

@@ -11,7 +11,8 @@ import torch
 
 from paper_1808_06992_amd import synth
 
-from parity import check_lasso_estimation, check_var_estimation, words_to_bool
+from parity import (check_lasso_estimation, check_var_estimation, check_var_per_equation,
+                    words_to_bool)
 
 pytestmark = pytest.mark.gpu
 
@@ -193,3 +194,45 @@ def test_uoi_var_order_d_and_intercept(api, orc, d, intercept, p, precision):
     mism = np.argwhere(got != want)
     assert mism.shape[0] <= 2, f"support mismatches {mism.tolist()}"
     check_var_estimation(orc, pr.series, seed, out, ref, d=d, intercept=intercept)
+
+
+def test_uoi_var_per_equation_choice(api, orc):
+    """Every equation chooses its own support index per split (UOI_FLAG_PER_EQUATION):
+    supports as the joint fit's, per-equation losses against oracle refits on the
+    GPU's supports, per-equation j*, and A and mu from the chosen refits."""
+    seed, d = 8, 2
+    pr = synth.var_d(12, 600, d, 0.15, 0.8, 5, mu_scale=1.0, intercept=True, burn=50, q=6, B1=4, B2=4)
+    ref = orc.uoi_var_d(pr.series, pr.lambdas, pr.B1, pr.B2, seed, d=d, intercept=True, per_equation=True)
+    assert ref["status"] == 0
+    out = api.var_fit(cuda(pr.series), pr.lambdas, pr.B1, pr.B2, seed, d=d, intercept=True,
+                      per_equation=True, kkt_tol=1e-10)
+    assert out["status"] == 0
+    assert out["jstar"].shape == (pr.B2, 12) and out["losses"].shape == (pr.B2, 6, 12)
+    mism = np.argwhere(words_to_bool(out["supports"].cpu().numpy(), d * 12) != words_to_bool(ref["supports"], d * 12))
+    assert mism.shape[0] <= 2, f"support mismatches {mism.tolist()}"
+    check_var_per_equation(orc, pr.series, seed, out, ref, d=d, intercept=True)
+
+
+def test_ingest_command_line_var_fit(api, tmp_path):
+    """The command-line front end reads a series file, builds the lambda grid and
+    fits on the GPU: the same results as the binding called directly."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    pr = synth.var_d(8, 400, 2, 0.2, 0.8, 3, mu_scale=1.0, intercept=True, burn=50, q=5, B1=3, B2=3)
+    np.save(tmp_path / "s.npy", pr.series)
+    out = tmp_path / "fit.npz"
+    r = subprocess.run([sys.executable, "-m", "paper_1808_06992_amd.ingest", "var", "--series",
+                        str(tmp_path / "s.npy"), "--order", "2", "--intercept", "--B1", "3", "--B2", "3",
+                        "--q", "5", "--precision", "fp64", "--kkt-tol", "1e-10", "--out", str(out)],
+                       cwd=root, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stdout + r.stderr
+    with np.load(out, allow_pickle=False) as f:
+        res = {k: f[k] for k in f.files}
+    np.testing.assert_allclose(res["lambdas"], pr.lambdas, rtol=1e-12)
+    ref = api.var_fit(cuda(pr.series), res["lambdas"], 3, 3, 0, d=2, intercept=True, kkt_tol=1e-10,
+                      precision="fp64", relax=1.8)
+    assert np.array_equal(res["A"], ref["A"].cpu().numpy())
+    assert np.array_equal(res["mu"], ref["mu"].cpu().numpy())
+    assert np.array_equal(res["supports"], ref["supports"].cpu().numpy().view(np.uint64))

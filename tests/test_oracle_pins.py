@@ -510,6 +510,53 @@ def test_uoi_var_d_composition(orc, d, intercept):
         assert np.all(r["mu"] == 0.0)
 
 
+def test_var_per_equation_choice(orc):
+    """Per-equation choice of the support index: each equation's j* is the argmin
+    of its own loss (recomputed in numpy with LAPACK refits), the losses summed
+    over equations equal the joint variant's losses, and with a single equation
+    (p = 1) the two variants coincide."""
+    d = 2
+    pr = synth.var_d(5, 300, d, 0.3, 0.8, 3, mu_scale=1.0, intercept=True, burn=50, q=4, B1=3, B2=3)
+    s = pr.series
+    T, p = s.shape
+    N, P = T - d, d * p
+    L = orc.var_block_len(N)
+    joint = orc.uoi_var_d(s, pr.lambdas, pr.B1, pr.B2, 9, d=d, intercept=True)
+    pe = orc.uoi_var_d(s, pr.lambdas, pr.B1, pr.B2, 9, d=d, intercept=True, per_equation=True)
+    assert pe["status"] == 0 and np.array_equal(pe["supports"], joint["supports"])
+    np.testing.assert_allclose(pe["losses"].sum(axis=2), joint["losses"], rtol=1e-12)
+    assert np.array_equal(pe["jstar"], np.argmin(pe["losses"], axis=1))
+    Xl, Yl = _lagged(s, d)
+    q = pr.lambdas.size
+    accA, accm = np.zeros((p, P)), np.zeros(p)
+    for k in range(pr.B2):
+        tr, ev = orc.var_split_rows(9, k, N, L)
+        for e in range(p):
+            best, bestL, fb, mb = None, None, None, None
+            for j in range(q):
+                S = sorted(_bits_to_set(pe["supports"][j, e], P))
+                Z = np.hstack([np.ones((tr.size, 1)), Xl[tr][:, S]])
+                coef = np.linalg.lstsq(Z, Yl[tr, e], rcond=None)[0]
+                f = np.zeros(P)
+                f[S] = coef[1:]
+                res = Yl[ev, e] - coef[0] - Xl[ev] @ f
+                Le = res @ res / ev.size
+                np.testing.assert_allclose(pe["losses"][k, j, e], Le, rtol=1e-9)
+                if best is None or Le < bestL:
+                    best, bestL, fb, mb = j, Le, f, coef[0]
+            assert pe["jstar"][k, e] == best
+            accA[e] += fb
+            accm[e] += mb
+    np.testing.assert_allclose(pe["A"], (accA / pr.B2).reshape(p, d, p).transpose(1, 0, 2), rtol=1e-9,
+                               atol=1e-13)
+    np.testing.assert_allclose(pe["mu"], accm / pr.B2, rtol=1e-9, atol=1e-12)
+    one = synth.var_d(1, 300, d, 1.0, 0.7, 5, intercept=True, burn=20, q=4, B1=3, B2=3)
+    a = orc.uoi_var_d(one.series, one.lambdas, 3, 3, 2, d=d, intercept=True)
+    b = orc.uoi_var_d(one.series, one.lambdas, 3, 3, 2, d=d, intercept=True, per_equation=True)
+    assert np.array_equal(a["jstar"], b["jstar"][:, 0])
+    np.testing.assert_array_equal(a["A"], b["A"])
+
+
 def test_var_intercept_translation_invariance(orc):
     """With an intercept, adding a constant c to every observation leaves every
     centred sample unchanged: the same supports and A, and mu-hat moves by
