@@ -80,6 +80,9 @@ def parse():
     ap.add_argument("--cpu-boots", type=int, default=48,
                     help="bootstraps of the CPU oracle sample (B1 = B2 = this)")
     ap.add_argument("--mlp-seeds", type=int, default=4, help="design seeds of the network's training set")
+    ap.add_argument("--tune-file", metavar="PATH",
+                    help="the library's autotuner reads recorded launch shapes from PATH and appends new ones "
+                         "(UOI_TUNE_FILE); counter runs use it so that no tuning launch is counted")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 1 GiB device copy first (scale of the HBM counters)")
     ap.add_argument("--summarize-trace", metavar="DIR", help="print a kernel-time summary and exit")
@@ -342,6 +345,8 @@ def main():
         print(f"bench.py: runs on one GPU (asked for --gpus {a.gpus}); splitting the bootstraps "
               "over several GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
+    if a.tune_file:
+        os.environ["UOI_TUNE_FILE"] = os.path.abspath(a.tune_file)
     import torch
     from paper_1808_06992_amd import _lib as api
     from paper_1808_06992_amd import synth
