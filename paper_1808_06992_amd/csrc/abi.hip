@@ -348,13 +348,17 @@ static int lasso_fit(int n, int p, const double *X, const double *y, const uoi_o
     P.tune = (o->flags & UOI_FLAG_NO_TUNE) == 0;
     EstimProblem E{B2, p, 1, q, R, nullptr, nullptr, nullptr, nullptr, nullptr, supp_out, o->cg_max_iter};
     size_t nst = (size_t)B1 * p * R;
+    // partial tiles of the selection product and of the evaluation product (over
+    // any column count up to p: the union of the supports is not known yet)
+    size_t gp_bytes = gram_part_bytes(B1, n, p, 1, true, 0, true);
+    for (int pp = 1; pp <= p; ++pp) gp_bytes = std::max(gp_bytes, gram_part_bytes(B2, nev, pp, 1, true, 1, false));
     // size the scratch arena
     Arena ar;
     auto layout = [&](Arena &a, int32_t *&rows, double *&G, double *&c, double *&lam, double *&z,
                       double *&u, int32_t *&its, double *&kkt, uint8_t *&flag, int32_t *&tr,
                       int32_t *&ev, double *&GT, double *&CT, double *&GE, double *&CE, double *&sE,
                       void *&admm_w, void *&est_w, void *&cw, int32_t *&gidx, uint64_t *&cs, double *&XU,
-                      double *&bc) {
+                      double *&bc, void *&gp) {
         // draws, counts, distinct rows, weights, sizes, input check flags, union size
         rows = a.take<int32_t>((size_t)4 * B1 * n + B1 + 8 + q);  // + union count and support sizes
         G = a.take<double>((size_t)B1 * p * p);
@@ -379,19 +383,20 @@ static int lasso_fit(int n, int p, const double *X, const double *y, const uoi_o
         cs = a.take<uint64_t>((size_t)q * ((p + 63) / 64));
         XU = a.take<double>((size_t)n * p);
         bc = a.take<double>(p);
+        gp = a.take<char>(gp_bytes);
     };
     int32_t *rows, *its, *tr, *ev, *gidx;
     double *G, *c, *lam, *z, *u, *kkt, *GT, *CT, *GE, *CE, *sE, *XU, *bc;
     uint8_t *flag;
     uint64_t *cs;
-    void *admm_w, *est_w, *cw;
+    void *admm_w, *est_w, *cw, *gp;
     layout(ar, rows, G, c, lam, z, u, its, kkt, flag, tr, ev, GT, CT, GE, CE, sE, admm_w, est_w, cw, gidx, cs,
-           XU, bc);
+           XU, bc, gp);
     Arena A;
     A.cap = ar.off;
     A.base = (char *)pool_get(ar.off);
     layout(A, rows, G, c, lam, z, u, its, kkt, flag, tr, ev, GT, CT, GE, CE, sE, admm_w, est_w, cw, gidx, cs,
-           XU, bc);
+           XU, bc, gp);
     check_finite(s, rows + (size_t)4 * B1 * n + B1, {{X, (size_t)n * p, "X"}, {y, (size_t)n, "y"}});
 
     Timer tm(s, timing);
@@ -415,7 +420,7 @@ static int lasso_fit(int n, int p, const double *X, const double *y, const uoi_o
         int32_t *nd = dw + (size_t)B1 * n;
         launch_distinct_rows(s, B1, n, n, rows, cntb, drow, dw, nd);
         gram_timer.start();
-        launch_gram_f64_weighted(s, B1, n, drow, dw, nd, n, p, X, p, 1, y, 1, G, c);
+        launch_gram_f64_weighted(s, B1, n, drow, dw, nd, n, p, X, p, 1, y, 1, G, c, nullptr, gp, gp_bytes);
         gram_timer.stop();
     }
     tm.mark();
@@ -449,7 +454,7 @@ static int lasso_fit(int n, int p, const double *X, const double *y, const uoi_o
     // evaluation products directly; training products as their complement in the
     // full-data product (the split partitions the rows), so the larger training
     // side is never gathered
-    launch_gram_f64(s, B2, nev, ev, nullptr, pE, XE, pE, 1, y, 1, GE, CE, sE, 1);
+    launch_gram_f64(s, B2, nev, ev, nullptr, pE, XE, pE, 1, y, 1, GE, CE, sE, 1, gp, gp_bytes);
     launch_train_from_eval(s, B2, n, pE, XE, pE, 1, y, 1, GE, CE, ntr, nev, nullptr, nullptr, GT, CT, cw);
     tm.mark();
     E.GT = GT; E.CT = CT; E.GE = GE; E.CE = CE; E.sE = sE;
@@ -527,8 +532,11 @@ static int var_fit(int T, int p, int d, const double *series, int block_len, con
         double *xS, *yS, *xE, *yE, *xT, *yT, *xA, *yA, *beta;  // means (intercept), beta* (d > 1)
         uint64_t *supp;                                       // internal-order supports (d > 1)
         uint8_t *flag;
-        void *admm_w, *est_w, *cw;
+        void *admm_w, *est_w, *cw, *gp;
     } bf{};
+    // partial tiles of the selection and evaluation products
+    const size_t gp_bytes = std::max(gram_part_bytes(B1, N, P, pe, true, 0, true),
+                                     gram_part_bytes(B2, N, P, pe, true, 1, false));
     auto layout = [&](Arena &a, Buf &x) {
         // draws, counts, distinct rows, weights, sizes, input check flag
         x.rows = a.take<int32_t>((size_t)4 * B1 * N + B1 + 4);
@@ -566,6 +574,7 @@ static int var_fit(int T, int p, int d, const double *series, int block_len, con
         x.admm_w = a.take<char>(admm_work_bytes(Pb, o->precision, o->solver));
         x.est_w = a.take<char>(estim_work_bytes(E));
         x.cw = a.take<char>(complement_work_bytes(N, P, pe));
+        x.gp = a.take<char>(gp_bytes);
     };
     Arena ar;
     layout(ar, bf);
@@ -599,7 +608,8 @@ static int var_fit(int T, int p, int d, const double *series, int block_len, con
         int32_t *nd = dw + (size_t)B1 * N;
         launch_distinct_rows(s, B1, N, N, bf.rows, cntb, drow, dw, nd);
         gram_timer.start();
-        launch_gram_f64_weighted(s, B1, N, drow, dw, nd, N, P, Xd, p, pe, Yd, p, bf.G, bf.C);
+        launch_gram_f64_weighted(s, B1, N, drow, dw, nd, N, P, Xd, p, pe, Yd, p, bf.G, bf.C, nullptr, bf.gp,
+                                 gp_bytes);
         gram_timer.stop();
         if (icpt) {  // every bootstrap sample centred by its own means
             launch_colmeans(s, B1, N, drow, dw, nd, N, P, Xd, p, pe, Yd, p, bf.xS, bf.yS);
@@ -619,7 +629,7 @@ static int var_fit(int T, int p, int d, const double *series, int block_len, con
     launch_support_and(s, B1, P, R, bf.z, supp);
     tm.mark();
     UOI_HIP(hipStreamWaitEvent(s, ax.e2, 0));  // the splits
-    launch_gram_f64(s, B2, N, bf.ev, bf.nev, P, Xd, p, pe, Yd, p, bf.GE, bf.CE, nullptr, 1);
+    launch_gram_f64(s, B2, N, bf.ev, bf.nev, P, Xd, p, pe, Yd, p, bf.GE, bf.CE, nullptr, 1, bf.gp, gp_bytes);
     launch_colsq(s, B2, N, bf.ev, bf.nev, pe, Yd, p, bf.sE);
     launch_train_from_eval(s, B2, N, P, Xd, p, pe, Yd, p, bf.GE, bf.CE, 0, 0, bf.ntr, bf.nev, bf.GT, bf.CT,
                            bf.cw);
@@ -778,8 +788,10 @@ int uoi_gram(int32_t nb, int32_t m, const int32_t *rows, int32_t p, const double
         UOI_REQUIRE(rows && X && G, "NULL pointer");
         UOI_REQUIRE(pe == 0 || (Y && C && ldy >= pe), "pe > 0 needs Y, C and ldy >= pe");
         // the instance for products other than the fits' selection Grams
+        const size_t pb = gram_part_bytes(nb, m, p, pe, pe > 0, 1, false);
+        void *part = pb ? pool_get(pb) : nullptr;
         launch_gram_f64((hipStream_t)stream, nb, m, rows, nullptr, p, X, ldx, pe, Y, ldy, G,
-                        pe ? C : nullptr, nullptr, 1);
+                        pe ? C : nullptr, nullptr, 1, part, pb);
         UOI_HIP(hipStreamSynchronize((hipStream_t)stream));
         return UOI_OK;
     });

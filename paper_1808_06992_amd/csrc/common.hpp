@@ -236,16 +236,23 @@ void launch_expand_blocks(hipStream_t s, int nb, int nblk, int N, int L, const u
 // Gram: G[b] = X_r'X_r/m (full symmetric storage), C[b] = X_r'Y_r/m; per-batch row
 // counts may be given (mcount != nullptr) with row lists at stride m.  When pe < 32
 // and ss != nullptr, ss[b][e] = sum_r Y[r][e]^2 / m comes out of the same product.
+// part (part_bytes) holds the partial tiles of the split last round (see
+// gram_part_bytes); with nullptr or too little room nothing is split.
 void launch_gram_f64(hipStream_t s, int nb, int m, const int32_t *rows, const int32_t *mcount,
                      int p, const double *X, int ldx, int pe, const double *Y, int ldy,
-                     double *G, double *C, double *ss = nullptr, int role = 0);
+                     double *G, double *C, double *ss = nullptr, int role = 0, void *part = nullptr,
+                     size_t part_bytes = 0);
 // Weighted form over distinct rows: G[b] = sum_r w[b][r] x_r x_r' / div (likewise
 // C, ss), rows and weights at stride m, mcount[b] of them.  With w the draw
 // multiplicities and div the number of draws this equals the Gram of the sample
 // with repeated rows.
 void launch_gram_f64_weighted(hipStream_t s, int nb, int m, const int32_t *rows, const int32_t *w,
                               const int32_t *mcount, int div, int p, const double *X, int ldx, int pe,
-                              const double *Y, int ldy, double *G, double *C, double *ss = nullptr);
+                              const double *Y, int ldy, double *G, double *C, double *ss = nullptr,
+                              void *part = nullptr, size_t part_bytes = 0);
+// Bytes of partial tiles a product of these sizes splits into on the current
+// device (have_c: C is produced; role and weighted name the kernel instance).
+size_t gram_part_bytes(int nb, int m, int p, int pe, bool have_c, int role, bool weighted);
 // G[b][j][i] = G[b][i][j] for i > j (upper triangle from the lower one)
 void launch_symmetrize(hipStream_t s, int nb, int p, double *G);
 // sum of squares of Y columns over sampled rows / m:  ss[b*pe + e]

@@ -15,8 +15,17 @@
 // next chunk's gathered values are loaded into registers while the current
 // chunk is multiplied, and the row indices two chunks ahead, so the index ->
 // value dependency never stalls the MFMAs.  4 waves each own a 64x64 quadrant
-// as 4x4 MFMA 16x16x4 blocks.  The upper triangle is filled afterwards by a
-// coalesced transpose.
+// as 4x4 MFMA 16x16x4 blocks.
+//
+// Last partial round: with S workgroup slots on the chip (CUs x resident
+// workgroups per CU) and U tiles, the U mod S tiles of the last round would run
+// on a partly idle chip.  Those tiles are split over their rows into f parts
+// (f <= 4, f * (U mod S) <= S) that run side by side; each part stores its raw
+// accumulators and k_gram_fixup adds the parts in part order, so the result does
+// not depend on timing (it differs from an unsplit tile at rounding level only).
+#include <map>
+#include <mutex>
+
 #include "common.hpp"
 
 namespace uoi {
@@ -41,7 +50,45 @@ struct GramArgs {
     int T, Tc;
     const int32_t *wt;   // per-row weights (multiplicities) at stride m, or null
     int div;             // divisor of the sums (0: the row count)
+    int tiles;           // tiles per batch entry
+    int nfull;           // units 0..nfull-1 are whole tiles (batch-entry major)
+    int fsplit;          // parts of each later tile (1: none split)
+    double *part;        // raw partial tiles of the split units [unit - nfull][GT * GT]
 };
+
+// tile index within a batch entry -> tile coordinates (lower triangle, then C tiles)
+__device__ __forceinline__ void tile_coords(const GramArgs &g, int tile, int &ti, int &tj, bool &isC) {
+    const int ntri = g.T * (g.T + 1) / 2;
+    if (tile < ntri) {
+        // row-major over the lower triangle, tj <= ti
+        ti = (int)((sqrt(8.0 * tile + 1.0) - 1.0) * 0.5);
+        while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
+        while (ti * (ti + 1) / 2 > tile) --ti;
+        tj = tile - ti * (ti + 1) / 2;
+        isC = false;
+    } else {
+        tile -= ntri;
+        ti = tile / g.Tc;
+        tj = tile % g.Tc;
+        isC = true;
+    }
+}
+
+// Store product entry (i, j) of batch entry b, already divided by the row count.
+__device__ __forceinline__ void gram_store(const GramArgs &g, int b, int i, int j, bool isC, double v) {
+    const size_t gb = (size_t)b * g.p;
+    const int naug = g.p + g.pa;
+    if (isC) {
+        if (i < g.p && j < g.pe) g.C[(gb + i) * g.pe + j] = v;
+    } else if (j <= i && i < naug) {
+        if (i < g.p) {                                   // design block, both halves
+            g.G[(gb + i) * g.p + j] = v;
+            if (j < i) g.G[(gb + j) * g.p + i] = v;
+        }
+        else if (j < g.p) g.C[(gb + j) * g.pa + (i - g.p)] = v;  // X'y block
+        else if (i == j && g.ss) g.ss[(size_t)b * g.pa + (i - g.p)] = v;  // y'y diagonal
+    }
+}
 
 // value of augmented column j of sampled row r
 __device__ __forceinline__ double aug_col(const GramArgs &g, size_t r, int j) {
@@ -56,24 +103,16 @@ template <int ROLE, bool WGT>
 __global__ __launch_bounds__(256, 2) void k_gram_f64(GramArgs g) {
     __shared__ double As[GK][GT];
     __shared__ double Bs[GK][GT];
-    const int b = blockIdx.y;
-    int tile = blockIdx.x;
-    const int ntri = g.T * (g.T + 1) / 2;
+    // unit -> (tile of batch entry b, part q of f)
+    const int u = blockIdx.x;
+    const int su = u - g.nfull;                      // index among split units, or < 0
+    const int f = su < 0 ? 1 : g.fsplit;
+    const int q = su < 0 ? 0 : su % f;
+    const int lt = su < 0 ? u : g.nfull + su / f;
+    const int b = lt / g.tiles;
     int ti, tj;
     bool isC;
-    if (tile < ntri) {
-        // tile -> (ti, tj) with tj <= ti, row-major over the lower triangle
-        ti = (int)((sqrt(8.0 * tile + 1.0) - 1.0) * 0.5);
-        while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
-        while (ti * (ti + 1) / 2 > tile) --ti;
-        tj = tile - ti * (ti + 1) / 2;
-        isC = false;
-    } else {
-        tile -= ntri;
-        ti = tile / g.Tc;
-        tj = tile % g.Tc;
-        isC = true;
-    }
+    tile_coords(g, lt % g.tiles, ti, tj, isC);
     const int i0 = ti * GT, j0 = tj * GT;
     const int mb = g.mcount ? g.mcount[b] : g.m;
     const int32_t *rb = g.rows + (size_t)b * g.m;
@@ -141,14 +180,16 @@ __global__ __launch_bounds__(256, 2) void k_gram_f64(GramArgs g) {
         }
     };
 
+    // this unit's chunks of GK rows: [c0, c1)
     const int nchunk = (mb + GK - 1) / GK;
-    load_idx(0, idx1, wi1);
-    load_val(0, idx1);
+    const int c0 = (int)((int64_t)q * nchunk / f), c1 = (int)((int64_t)(q + 1) * nchunk / f);
+    load_idx(c0 * GK, idx1, wi1);
+    load_val(c0 * GK, idx1);
     store(wi1);
-    load_idx(GK, idx1, wi1);
+    load_idx((c0 + 1) * GK, idx1, wi1);
     __syncthreads();
-    for (int c = 0; c < nchunk; ++c) {
-        const bool more = c + 1 < nchunk;
+    for (int c = c0; c < c1; ++c) {
+        const bool more = c + 1 < c1;
         if (more) {
             load_val((c + 1) * GK, idx1);        // values of chunk c+1
             load_idx((c + 2) * GK, idx2, wi2);   // indices and weights of chunk c+2
@@ -177,28 +218,48 @@ __global__ __launch_bounds__(256, 2) void k_gram_f64(GramArgs g) {
         __syncthreads();
     }
 
+    if (su >= 0) {  // a part of a split tile: raw accumulators, in register order
+        double *P = g.part + (size_t)su * GT * GT;
+#pragma unroll
+        for (int fm = 0; fm < 4; ++fm)
+#pragma unroll
+            for (int fn = 0; fn < 4; ++fn)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) P[((((wid * 4 + fm) * 4 + fn) * 4 + t) << 6) + lane] = acc[fm][fn][t];
+        return;
+    }
     const double inv = 1.0 / (double)(g.div > 0 ? g.div : mb);
-    const size_t gb = (size_t)b * g.p;
 #pragma unroll
     for (int fm = 0; fm < 4; ++fm)
 #pragma unroll
         for (int fn = 0; fn < 4; ++fn)
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int i = i0 + wm * 64 + fm * 16 + mfma_row(0.0, lk, t);
-                const int j = j0 + wn * 64 + fn * 16 + lr;
-                const double v = acc[fm][fn][t] * inv;
-                if (isC) {
-                    if (i < g.p && j < g.pe) g.C[(gb + i) * g.pe + j] = v;
-                } else if (j <= i && i < naug) {
-                    if (i < g.p) {                                   // design block, both halves
-                        g.G[(gb + i) * g.p + j] = v;
-                        if (j < i) g.G[(gb + j) * g.p + i] = v;
-                    }
-                    else if (j < g.p) g.C[(gb + j) * g.pa + (i - g.p)] = v;  // X'y block
-                    else if (i == j && g.ss) g.ss[(size_t)b * g.pa + (i - g.p)] = v;  // y'y diagonal
-                }
-            }
+            for (int t = 0; t < 4; ++t)
+                gram_store(g, b, i0 + wm * 64 + fm * 16 + mfma_row(0.0, lk, t), j0 + wn * 64 + fn * 16 + lr, isC,
+                           acc[fm][fn][t] * inv);
+}
+
+// Split tiles: the sum of their parts in part order, divided by the row count.
+// One workgroup per split tile, threads laid out as in k_gram_f64.
+__global__ __launch_bounds__(256) void k_gram_fixup(GramArgs g) {
+    const int lt = g.nfull + blockIdx.x;
+    const int b = lt / g.tiles;
+    int ti, tj;
+    bool isC;
+    tile_coords(g, lt % g.tiles, ti, tj, isC);
+    const int i0 = ti * GT, j0 = tj * GT;
+    const int mb = g.mcount ? g.mcount[b] : g.m;
+    const double inv = 1.0 / (double)(g.div > 0 ? g.div : mb);
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int wm = wid >> 1, wn = wid & 1, lr = lane & 15, lk = lane >> 4;
+    const double *P = g.part + (size_t)blockIdx.x * g.fsplit * GT * GT;
+    for (int r = 0; r < 64; ++r) {  // r = (fm, fn, t)
+        const int fm = r >> 4, fn = (r >> 2) & 3, t = r & 3;
+        const size_t o = ((size_t)(wid * 64 + r) << 6) + lane;
+        double v = P[o];
+        for (int h = 1; h < g.fsplit; ++h) v += P[(size_t)h * GT * GT + o];
+        gram_store(g, b, i0 + wm * 64 + fm * 16 + mfma_row(0.0, lk, t), j0 + wn * 64 + fn * 16 + lr, isC, v * inv);
+    }
 }
 
 // Upper triangle from the lower one: G[j][i] = G[i][j] for i > j, by 32x32
@@ -247,39 +308,118 @@ __global__ __launch_bounds__(256) void k_colsq(int m, const int32_t *__restrict_
     }
 }
 
+namespace {
+// Workgroup slots of a Gram instance on the current device: CUs x workgroups of
+// that instance resident per CU.
+template <int ROLE, bool WGT>
+int gram_slots() {
+    static std::mutex mu;
+    static std::map<int, int> cache;
+    int dev = 0;
+    UOI_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(dev);
+    if (it != cache.end()) return it->second;
+    int cus = 0, per = 0;
+    UOI_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    UOI_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void *>(&k_gram_f64<ROLE, WGT>),
+                                                         256, 0));
+    const int slots = std::max(1, cus * std::max(per, 1));
+    cache[dev] = slots;
+    return slots;
+}
+
+int gram_slots_of(int role, bool weighted) {
+    if (weighted) return gram_slots<0, true>();
+    return role == 0 ? gram_slots<0, false>() : gram_slots<1, false>();
+}
+
+// Tile counts of a product (see GramArgs) and the split of its last partial round.
+struct GramPlan {
+    int T, Tc, pa, pe, tiles, nfull, f, units;
+    size_t part_bytes;
+};
+
+GramPlan gram_plan(int nb, int m, int p, int pe, bool have_c, int slots) {
+    GramPlan pl{};
+    const bool aug = have_c && pe > 0 && pe < AUG_MAX;
+    pl.pa = aug ? pe : 0;
+    pl.pe = (have_c && !aug) ? pe : 0;
+    pl.T = (int)cdiv(p + pl.pa, GT);
+    pl.Tc = pl.pe > 0 ? (int)cdiv(pl.pe, GT) : 0;
+    pl.tiles = pl.T * (pl.T + 1) / 2 + (int)cdiv(p, GT) * pl.Tc;
+    const int64_t total = (int64_t)nb * pl.tiles;
+    const int rem = (int)(total % slots);  // tiles of the last, partial round
+    int f = rem ? std::min(4, slots / rem) : 1;
+    f = std::min<int64_t>(f, std::max<int64_t>(1, cdiv(m, GK) / 4));  // at least 4 chunks per part
+    if (f < 2) {
+        pl.f = 1;
+        pl.nfull = (int)total;
+        pl.units = (int)total;
+        pl.part_bytes = 0;
+    } else {
+        pl.f = f;
+        pl.nfull = (int)(total - rem);
+        pl.units = pl.nfull + rem * f;
+        pl.part_bytes = sizeof(double) * (size_t)rem * f * GT * GT;
+    }
+    return pl;
+}
+
+// Launch a product planned by gram_plan; without room for the partial tiles no
+// tile is split.
+void run_gram(hipStream_t s, GramArgs g, GramPlan pl, int role, bool weighted, void *part, size_t part_bytes) {
+    if (pl.f > 1 && (part == nullptr || part_bytes < pl.part_bytes)) {
+        const int rem = (pl.units - pl.nfull) / pl.f;
+        pl.f = 1;
+        pl.nfull = pl.units = pl.nfull + rem;
+    }
+    g.pa = pl.pa;
+    g.pe = pl.pe;
+    g.T = pl.T;
+    g.Tc = pl.Tc;
+    g.tiles = pl.tiles;
+    g.nfull = pl.nfull;
+    g.fsplit = pl.f;
+    g.part = (double *)part;
+    if (pl.units == 0) return;
+    if (weighted)
+        hipLaunchKernelGGL((k_gram_f64<0, true>), dim3(pl.units), dim3(256), 0, s, g);
+    else if (role == 0)
+        hipLaunchKernelGGL((k_gram_f64<0, false>), dim3(pl.units), dim3(256), 0, s, g);
+    else
+        hipLaunchKernelGGL((k_gram_f64<1, false>), dim3(pl.units), dim3(256), 0, s, g);
+    UOI_LAUNCH_CHECK();
+    if (pl.f > 1) {
+        hipLaunchKernelGGL(k_gram_fixup, dim3((pl.units - pl.nfull) / pl.f), dim3(256), 0, s, g);
+        UOI_LAUNCH_CHECK();
+    }
+}
+}  // namespace
+
+size_t gram_part_bytes(int nb, int m, int p, int pe, bool have_c, int role, bool weighted) {
+    return gram_plan(nb, m, p, pe, have_c, gram_slots_of(role, weighted)).part_bytes;
+}
+
 void launch_gram_f64(hipStream_t s, int nb, int m, const int32_t *rows, const int32_t *mcount,
                      int p, const double *X, int ldx, int pe, const double *Y, int ldy,
-                     double *G, double *C, double *ss, int role) {
+                     double *G, double *C, double *ss, int role, void *part, size_t part_bytes) {
     GramArgs g{};
     g.m = m; g.rows = rows; g.mcount = mcount; g.p = p; g.X = X; g.ldx = ldx;
     g.Y = Y; g.ldy = ldy; g.G = G; g.C = C; g.ss = ss;
-    const bool aug = C != nullptr && pe > 0 && pe < AUG_MAX;
-    g.pa = aug ? pe : 0;
-    g.pe = (C != nullptr && !aug) ? pe : 0;
-    g.T = (int)cdiv(p + g.pa, GT);
-    g.Tc = g.pe > 0 ? (int)cdiv(g.pe, GT) : 0;
-    const int tiles = g.T * (g.T + 1) / 2 + (int)cdiv(p, GT) * g.Tc;
-    if (role == 0)
-        hipLaunchKernelGGL((k_gram_f64<0, false>), dim3(tiles, nb), dim3(256), 0, s, g);
-    else
-        hipLaunchKernelGGL((k_gram_f64<1, false>), dim3(tiles, nb), dim3(256), 0, s, g);
-    UOI_LAUNCH_CHECK();
+    const GramPlan pl = gram_plan(nb, m, p, pe, C != nullptr, gram_slots_of(role, false));
+    run_gram(s, g, pl, role, false, part, part_bytes);
 }
 
 void launch_gram_f64_weighted(hipStream_t s, int nb, int m, const int32_t *rows, const int32_t *w,
                               const int32_t *mcount, int div, int p, const double *X, int ldx, int pe,
-                              const double *Y, int ldy, double *G, double *C, double *ss) {
+                              const double *Y, int ldy, double *G, double *C, double *ss, void *part,
+                              size_t part_bytes) {
     GramArgs g{};
     g.m = m; g.rows = rows; g.mcount = mcount; g.p = p; g.X = X; g.ldx = ldx;
     g.Y = Y; g.ldy = ldy; g.G = G; g.C = C; g.ss = ss; g.wt = w; g.div = div;
-    const bool aug = C != nullptr && pe > 0 && pe < AUG_MAX;
-    g.pa = aug ? pe : 0;
-    g.pe = (C != nullptr && !aug) ? pe : 0;
-    g.T = (int)cdiv(p + g.pa, GT);
-    g.Tc = g.pe > 0 ? (int)cdiv(g.pe, GT) : 0;
-    const int tiles = g.T * (g.T + 1) / 2 + (int)cdiv(p, GT) * g.Tc;
-    hipLaunchKernelGGL((k_gram_f64<0, true>), dim3(tiles, nb), dim3(256), 0, s, g);
-    UOI_LAUNCH_CHECK();
+    const GramPlan pl = gram_plan(nb, m, p, pe, C != nullptr, gram_slots_of(0, true));
+    run_gram(s, g, pl, 0, true, part, part_bytes);
 }
 
 void launch_symmetrize(hipStream_t s, int nb, int p, double *G) {
@@ -358,7 +498,8 @@ size_t complement_work_bytes(int n, int p, int pe) {
         const SliceShape sh = slice_shape(n, pp, pe);
         most = std::max(most, al(sizeof(int32_t) * (size_t)sh.ns * sh.mp) + al(sizeof(int32_t) * sh.ns) +
                                   al(sizeof(double) * (size_t)sh.ns * pp * (pp + pe)) +
-                                  al(sizeof(double) * (size_t)pp * (pp + pe)));
+                                  al(sizeof(double) * (size_t)pp * (pp + pe)) +
+                                  al(gram_part_bytes(sh.ns, sh.mp, pp, pe, true, 1, false)));
     }
     return most;
 }
@@ -379,10 +520,12 @@ void launch_train_from_eval(hipStream_t s, int nb, int n, int p, const double *X
     w += al(sizeof(double) * (size_t)sh.ns * p * (p + pe));
     double *SG = (double *)w;
     double *SC = SG + (size_t)p * p;
+    w += al(sizeof(double) * (size_t)p * (p + pe));
+    const size_t pb = gram_part_bytes(sh.ns, sh.mp, p, pe, true, 1, false);
 
     hipLaunchKernelGGL(k_row_slices, dim3(cdiv(sh.mp, 256), sh.ns), dim3(256), 0, s, n, sh.mp, rows, cnt);
     UOI_LAUNCH_CHECK();
-    launch_gram_f64(s, sh.ns, sh.mp, rows, cnt, p, X, ldx, pe, Y, ldy, Gp, Cp, nullptr, 1);
+    launch_gram_f64(s, sh.ns, sh.mp, rows, cnt, p, X, ldx, pe, Y, ldy, Gp, Cp, nullptr, 1, w, pb);
     const size_t lg = (size_t)p * p, lc = (size_t)p * pe;
     const int nbk = 1024;
     hipLaunchKernelGGL(k_sum_slices, dim3((unsigned)std::min<size_t>(cdiv(lg, 256), nbk)), dim3(256), 0,

@@ -71,6 +71,26 @@ def test_gram_parity(api, orc, n, p, m):
         assert np.array_equal(G[b], G[b].T)
 
 
+def test_gram_parity_split_last_round(api, orc):
+    """More single-tile products than one round of workgroup slots: on a 256-CU
+    part with two Gram workgroups per CU, 530 products leave 18 tiles for the
+    last round, which run split over their rows into 4 parts each (the smaller
+    cases above split every tile, the round being partial).  Every product
+    matches the oracle and stays symmetric."""
+    rng = np.random.default_rng(11)
+    n, p, m, nb = 400, 100, 300, 530
+    X = rng.standard_normal((n, p))
+    y = rng.standard_normal(n)
+    rows = rng.integers(0, n, size=(nb, m)).astype(np.int32)
+    G, c = api.gram(cuda(X), cuda(rows, torch.int32), cuda(y))
+    G, c = G.cpu().numpy(), c.cpu().numpy()
+    for b in range(nb):
+        Go, co = orc.gram(X, y, rows[b])
+        np.testing.assert_allclose(G[b], Go, rtol=1e-12, atol=1e-13)
+        np.testing.assert_allclose(c[b, :, 0], co, rtol=1e-12, atol=1e-13)
+        assert np.array_equal(G[b], G[b].T)
+
+
 def test_gram_var_parity(api, orc):
     pr = synth.var1(70, 400, 0.1, 0.8, 3, burn=20)
     N = pr.series.shape[0] - 1
