@@ -5,9 +5,10 @@
 //
 // tune_choose(s, key, n, run): if key has a recorded choice, returns it (the
 // caller then runs that candidate itself, ran_all = false).  Otherwise runs
-// run(c) for every candidate c on stream s between two events, waits, keeps the
-// fastest, and returns it with ran_all = true: the outputs of the last run are
-// in place, so the caller need not run again.  Choices are kept per device for
+// candidate 0 once untimed (warm-up), then run(c) for every candidate c on
+// stream s between two events, waits, keeps the fastest, and returns it with
+// ran_all = true: the outputs of the last run are in place, so the caller need
+// not run again.  Choices are kept per device for
 // the process and, when the environment variable UOI_TUNE_FILE names a file,
 // read from it at the first use and appended to it for every new key (one
 // "key choice" line each), so later processes reuse them.
@@ -63,6 +64,10 @@ TuneResult tune_choose(hipStream_t s, const std::string &key, int ncand, const s
     }
     std::vector<hipEvent_t> ev(2 * ncand);
     for (auto &e : ev) UOI_HIP(hipEventCreate(&e));
+    // one untimed run first: the first launches of a shape pay one-time costs
+    // (code loading, first touch of the workspace) that would bias the first
+    // candidate
+    run(0);
     for (int c = 0; c < ncand; ++c) {
         UOI_HIP(hipEventRecord(ev[2 * c], s));
         for (int r = 0; r < reps; ++r) run(c);

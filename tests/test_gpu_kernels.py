@@ -104,11 +104,12 @@ def test_gram_var_parity(api, orc):
 
 # --------------------------------------------------------------------------- inverse
 
-@pytest.mark.parametrize("p,nb", [(1, 2), (7, 2), (50, 2), (88, 2), (89, 2), (130, 2), (200, 2),
-                                  (257, 11)])
+@pytest.mark.parametrize("p,nb", [(1, 2), (7, 2), (50, 2), (88, 2), (89, 2), (130, 2), (192, 2), (200, 2),
+                                  (257, 11), (300, 3), (384, 2)])
 def test_spd_inverse_parity(api, orc, p, nb):
-    """Blocked sweeps with a ragged last pivot block (p = 257: one column), and a
-    batch that is not a multiple of the 8 XCDs."""
+    """Blocked sweeps of 64-wide pivot blocks with a ragged last block (p = 89,
+    130, 200, 257, 300: 25, 2, 8, 1 and 44 columns), blocks that end on p (192,
+    384), and a batch that is not a multiple of the 8 XCDs."""
     rng = np.random.default_rng(p)
     n = 3 * p + 10
     X = rng.standard_normal((n, p))
@@ -123,9 +124,8 @@ def test_spd_inverse_parity(api, orc, p, nb):
 
 @pytest.mark.parametrize("p,nb", [(1000, 7), (700, 48)])
 def test_spd_inverse_parity_many_tiles(api, p, nb):
-    """More tiles per block step than workgroups resident at once, so most tiles
-    are taken from the update's per-XCD queues; odd batch and a ragged last block
-    (p = 700)."""
+    """More tiles per block step than workgroups resident at once; an odd batch,
+    and ragged last pivot blocks of 40 (p = 1000) and 60 (p = 700) columns."""
     rng = np.random.default_rng(p + nb)
     n = 2 * p
     G = np.empty((nb, p, p))
