@@ -34,6 +34,15 @@ constexpr size_t kMidScratch = (size_t)256 << 20;  // bytes of factor storage pe
 constexpr double kCgTol = 1e-13;
 }
 
+// Orders the LDS accesses of one wave across its lanes (stores before it are
+// seen by loads after it): per lane, the compiler may otherwise move a load
+// above another lane's store.
+__device__ __forceinline__ void lane_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __global__ void k_popcount(int R, int W, const uint64_t *__restrict__ supp, int32_t *__restrict__ cnt) {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= R) return;
@@ -194,6 +203,7 @@ __global__ __launch_bounds__(256) void k_ols_mid(int p, int pe, int R, int W,
     __shared__ double Lp[64][LDP];           // staged rows kb..kb+kPW of the factor
     __shared__ double xv[kMid + 1];
     __shared__ double red[8][33];
+    __shared__ double colb[kPW], rdiag[kPW];
     __shared__ int fail;
     const int tid = threadIdx.x;
     const int k = sys[blockIdx.x].x, r = sys[blockIdx.x].y;
@@ -255,23 +265,66 @@ __global__ __launch_bounds__(256) void k_ols_mid(int p, int pe, int R, int W,
             }
             __syncthreads();
         }
-        // factor the panel in LDS
-        for (int c = 0; c < nbk; ++c) {
-            if (tid == 0) {
-                double d = Pn[c * LDP + c];
-                if (!(d > 0.0)) { fail = 1; d = 1.0; }
-                Pn[c * LDP + c] = sqrt(d);
+        // factor the panel: its nbk x nbk top block by one wave in registers,
+        // then every row below (and the right-hand side row) by a forward
+        // substitution against that block, one row per thread
+        if (tid < 64) {
+            const int c = tid & 15, r0 = tid >> 4;  // column c, rows r0 + 4a
+            double v[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const int r = r0 + 4 * a;
+                v[a] = (r < nbk && c < nbk) ? Pn[r * LDP + c] : (r == c ? 1.0 : 0.0);  // identity padding
             }
-            __syncthreads();
-            const double dc = Pn[c * LDP + c];
-            for (int i = c + 1 + tid; i < m; i += 256) Pn[i * LDP + c] /= dc;
-            __syncthreads();
-            for (int i = c + 1 + tid; i < m; i += 256) {
-                const double lic = Pn[i * LDP + c];
-                for (int c2 = c + 1; c2 < nbk && c2 <= i; ++c2) Pn[i * LDP + c2] -= lic * Pn[c2 * LDP + c];
+#pragma unroll
+            for (int j = 0; j < kPW; ++j) {
+                lane_sync();  // the previous step's reads are done
+                if (c == j) {
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) colb[r0 + 4 * a] = v[a];  // column j
+                }
+                lane_sync();
+                double d = colb[j];
+                if (!(d > 0.0)) {
+                    if (j < nbk && tid == 0) fail = 1;
+                    d = 1.0;
+                }
+                const double sd = sqrt(d), rsd = 1.0 / sd;
+                if (tid == 0) rdiag[j] = rsd;
+                const double lc = colb[c] * rsd;  // L[c][j]
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    const int r = r0 + 4 * a;
+                    const double lr = colb[r] * rsd;  // L[r][j]
+                    if (c == j) v[a] = r == j ? sd : (r > j ? lr : v[a]);
+                    else if (c > j && r >= c) v[a] = fma(-lr, lc, v[a]);
+                }
             }
-            __syncthreads();
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const int r = r0 + 4 * a;
+                if (r < nbk && c <= r) Pn[r * LDP + c] = v[a];
+            }
         }
+        __syncthreads();
+        for (int i = nbk + tid; i < m; i += 256) {
+            double l[kPW];
+#pragma unroll
+            for (int c = 0; c < kPW; ++c) l[c] = c < nbk ? Pn[i * LDP + c] : 0.0;
+#pragma unroll
+            for (int c = 0; c < kPW; ++c) {
+                if (c < nbk) {
+                    double t = l[c];
+#pragma unroll
+                    for (int c2 = 0; c2 < c; ++c2) t = fma(-l[c2], Pn[c * LDP + c2], t);
+                    l[c] = t * rdiag[c];
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < kPW; ++c)
+                if (c < nbk) Pn[i * LDP + c] = l[c];
+        }
+        __syncthreads();
         for (int q = tid; q < m * nbk; q += 256) {
             const int c = q / m, i = q % m;
             if (i >= c) L[(size_t)(kb + c) * ld + kb + i] = Pn[i * LDP + c];
