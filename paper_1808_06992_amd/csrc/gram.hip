@@ -17,12 +17,13 @@
 // value dependency never stalls the MFMAs.  4 waves each own a 64x64 quadrant
 // as 4x4 MFMA 16x16x4 blocks.
 //
-// Last partial round: with S workgroup slots on the chip (CUs x resident
-// workgroups per CU) and U tiles, the U mod S tiles of the last round would run
-// on a partly idle chip.  Those tiles are split over their rows into f parts
-// (f <= 4, f * (U mod S) <= S) that run side by side; each part stores its raw
-// accumulators and k_gram_fixup adds the parts in part order, so the result does
-// not depend on timing (it differs from an unsplit tile at rounding level only).
+// Short launches: with S workgroup slots on the chip (CUs x resident workgroups
+// per CU) and U < S tiles (the estimation products over the union's columns,
+// for instance), most of the chip would idle.  The tiles are then split over
+// their rows into f parts (f <= 4, f U <= S) that run side by side; each part
+// stores its raw accumulators and k_gram_fixup adds the parts in part order, so
+// the result does not depend on timing (it differs from an unsplit tile at
+// rounding level only).
 #include <map>
 #include <mutex>
 
@@ -349,7 +350,10 @@ GramPlan gram_plan(int nb, int m, int p, int pe, bool have_c, int slots) {
     pl.Tc = pl.pe > 0 ? (int)cdiv(pl.pe, GT) : 0;
     pl.tiles = pl.T * (pl.T + 1) / 2 + (int)cdiv(p, GT) * pl.Tc;
     const int64_t total = (int64_t)nb * pl.tiles;
-    const int rem = (int)(total % slots);  // tiles of the last, partial round
+    // Only a launch shorter than one round is split: after full rounds the last
+    // round's workgroups run alone on their compute units, faster than in a full
+    // round, and the fixup pass costs more than the split saves.
+    const int rem = total < slots ? (int)total : 0;
     int f = rem ? std::min(4, slots / rem) : 1;
     f = std::min<int64_t>(f, std::max<int64_t>(1, cdiv(m, GK) / 4));  // at least 4 chunks per part
     if (f < 2) {

@@ -71,14 +71,14 @@ def test_gram_parity(api, orc, n, p, m):
         assert np.array_equal(G[b], G[b].T)
 
 
-def test_gram_parity_split_last_round(api, orc):
-    """More single-tile products than one round of workgroup slots: on a 256-CU
-    part with two Gram workgroups per CU, 530 products leave 18 tiles for the
-    last round, which run split over their rows into 4 parts each (the smaller
-    cases above split every tile, the round being partial).  Every product
-    matches the oracle and stays symmetric."""
+@pytest.mark.parametrize("nb", [200, 530])
+def test_gram_parity_split_and_full_rounds(api, orc, nb):
+    """On a 256-CU part with two Gram workgroups per CU (512 slots): 200
+    single-tile products are each split in two over their rows (the cases above
+    split into four), 530 fill more than a round and run unsplit.  Every
+    product matches the oracle and stays symmetric."""
     rng = np.random.default_rng(11)
-    n, p, m, nb = 400, 100, 300, 530
+    n, p, m = 400, 100, 300
     X = rng.standard_normal((n, p))
     y = rng.standard_normal(n)
     rows = rng.integers(0, n, size=(nb, m)).astype(np.int32)
