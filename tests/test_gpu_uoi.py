@@ -236,3 +236,23 @@ def test_ingest_command_line_var_fit(api, tmp_path):
     assert np.array_equal(res["A"], ref["A"].cpu().numpy())
     assert np.array_equal(res["mu"], ref["mu"].cpu().numpy())
     assert np.array_equal(res["supports"], ref["supports"].cpu().numpy().view(np.uint64))
+
+
+@pytest.mark.gpu
+def test_pathwise_and_strong_rule_baselines(api):
+    """The non-learned baselines of the learned warm start on the n200 p50 fit:
+    lambda continuation in 2 and 4 blocks reaches the cold solutions (within the
+    KKT tolerance's reach), with iteration counts reported per block; the
+    sequential strong rule keeps every support feature of nearly every solve."""
+    from paper_1808_06992_amd import baselines
+    pr = synth.lasso_small(0)
+    r = baselines.pathwise(pr, 0, pr.B1, groups=(2, 4), kkt_tol=1e-10, precision="fp64")
+    assert r["cold"]["mean_iters"] > 0
+    for ng in (2, 4):
+        pw = r["path"][ng]
+        assert len(pw["block_max"]) == ng
+        assert pw["max_rel_diff"] < 1e-6, pw
+    sr = baselines.strong_rule(pr, 0, pr.B1)
+    assert sr["solves_screened"] == pr.B1 * (pr.lambdas.size - 1)
+    assert sr["kept_min"] >= 0 and sr["kept_mean"] >= sr["support_mean"]
+    assert sr["violations"] <= 0.01 * sr["solves_screened"] * sr["config"]["p"]
