@@ -71,14 +71,15 @@ def test_gram_parity(api, orc, n, p, m):
         assert np.array_equal(G[b], G[b].T)
 
 
-@pytest.mark.parametrize("nb", [200, 530])
-def test_gram_parity_split_and_full_rounds(api, orc, nb):
+@pytest.mark.parametrize("p,nb", [(100, 200), (100, 530), (300, 100)])
+def test_gram_parity_split_and_full_rounds(api, orc, p, nb):
     """On a 256-CU part with two Gram workgroups per CU (512 slots): 200
     single-tile products are each split in two over their rows (the cases above
-    split into four), 530 fill more than a round and run unsplit.  Every
-    product matches the oracle and stays symmetric."""
+    split into four), 530 fill more than a round and run unsplit.  At p = 300
+    (600 tiles) the unsplit launch also holds tiles off the diagonal and a ragged
+    last tile row.  Every product matches the oracle and stays symmetric."""
     rng = np.random.default_rng(11)
-    n, p, m = 400, 100, 300
+    n, m = 400, 300
     X = rng.standard_normal((n, p))
     y = rng.standard_normal(n)
     rows = rng.integers(0, n, size=(nb, m)).astype(np.int32)
