@@ -108,7 +108,9 @@ typedef struct uoi_opts {
     int32_t q;             /* number of lambdas, >= 1                                      */
     const double *lambdas; /* HOST, q values, strictly decreasing, >= 0                    */
     uint64_t seed;         /* drives every random choice (bootstrap rows, splits, blocks)  */
-    double rho;            /* ADMM penalty, > 0 (default 1)                                */
+    double rho;            /* ADMM penalty, > 0 (default 1); 0: scaled to the data, the    */
+                           /* mean diagonal of the Grams, read back once per solve (not    */
+                           /* for the allocation-free entry point)                          */
     double kkt_tol;        /* relative KKT tolerance, > 0 (default 1e-6)                   */
     int32_t max_iter;      /* ADMM iteration cap, >= 1 (default 20000)                     */
     int32_t check_every;   /* KKT check period in ADMM iterations, >= 1 (default 10)       */

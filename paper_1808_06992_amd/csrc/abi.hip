@@ -200,7 +200,7 @@ static void check_opts(const uoi_opts *o, bool need_boot) {
                     "lambdas must be finite and >= 0");
         if (j) UOI_REQUIRE(o->lambdas[j] < o->lambdas[j - 1], "lambdas must be strictly decreasing");
     }
-    UOI_REQUIRE(std::isfinite(o->rho) && o->rho > 0.0, "rho must be > 0");
+    UOI_REQUIRE(std::isfinite(o->rho) && o->rho >= 0.0, "rho must be >= 0 (0: scaled to the data)");
     UOI_REQUIRE(std::isfinite(o->kkt_tol) && o->kkt_tol > 0.0, "kkt_tol must be > 0");
     UOI_REQUIRE(o->max_iter >= 1, "max_iter must be >= 1");
     UOI_REQUIRE(o->check_every >= 1, "check_every must be >= 1");
@@ -693,6 +693,7 @@ int solve_batch(int nb, int p, const double *G, const double *c, const uoi_opts 
     const bool no_alloc = scratch_cap > 0;
     UOI_REQUIRE(!no_alloc || o->warm_start == UOI_COLD,
                 "the allocation-free entry point starts cold (no warm start by network)");
+    UOI_REQUIRE(!no_alloc || o->rho > 0.0, "the allocation-free entry point needs rho > 0");
     hipStream_t s = (hipStream_t)o->stream;
     const int q = o->q, R = q;
     AdmmProblem P{nb, p, q, 1, R, G, c, nullptr, o->rho, o->kkt_tol, o->max_iter, o->check_every,

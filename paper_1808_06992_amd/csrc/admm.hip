@@ -1013,9 +1013,48 @@ static int sweep(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T
     return active;
 }
 
+// Mean of the diagonals of nb p x p matrices (one workgroup; fixed summation
+// order, so the result does not depend on timing).  The result is written to
+// host memory that the device can reach.
+__global__ __launch_bounds__(256) void k_mean_diag(int nb, int p, const double *__restrict__ G,
+                                                   double *__restrict__ out) {
+    __shared__ double part[256];
+    const int64_t n = (int64_t)nb * p;
+    double acc = 0.0;
+    for (int64_t e = threadIdx.x; e < n; e += 256) {
+        const int64_t b = e / p, i = e - b * p;
+        acc += G[(b * p + i) * p + i];
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = part[0] / (double)n;
+}
+
+// The penalty when the caller passes rho = 0: the scale of the data, the mean
+// diagonal of the Grams (their average eigenvalue).  On standardised columns it
+// is about 1; on a VAR series it is the series' mean square, where rho = 1 is
+// far too small for the spectrum and ADMM converges many times more slowly.
+// Falls back to 1 for an all-zero design.
+double data_scaled_rho(hipStream_t s, int nb, int p, const double *G) {
+    double *h = (double *)pinned_slot(kPinnedScalar, sizeof(double));
+    hipLaunchKernelGGL(k_mean_diag, dim3(1), dim3(256), 0, s, nb, p, G, h);
+    UOI_LAUNCH_CHECK();
+    UOI_HIP(hipStreamSynchronize(s));
+    const double r = *h;
+    return std::isfinite(r) && r > 0.0 ? r : 1.0;
+}
+
 void admm_solve(hipStream_t s, const AdmmProblem &P0, int precision, int solver, void *work,
                 bool warm, AdmmOut &out, float *stage_ms) {
     AdmmProblem P = P0;  // the launch shapes (fn32, fn64) are filled in below
+    if (P.rho == 0.0) {
+        UOI_REQUIRE(!P.no_alloc, "rho = 0 (scaled to the data) reads a value back: not allocation-free");
+        P.rho = data_scaled_rho(s, P.nb, P.p, P.G);
+    }
     P.fn32 = P.fn64 = default_fn(P.R);
     Arena ar;
     ar.base = (char *)work;

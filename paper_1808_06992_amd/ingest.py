@@ -90,6 +90,8 @@ def main(argv=None) -> int:
         sp.add_argument("--kkt-tol", type=float, default=1e-6)
         sp.add_argument("--precision", choices=("fp64", "mixed"), default="mixed")
         sp.add_argument("--relax", type=float, default=1.8)
+        sp.add_argument("--rho", type=float, default=0.0,
+                        help="ADMM penalty; 0 (default) scales it to the data (mean diagonal of the Grams)")
         if name == "var":
             sp.add_argument("--series", required=True)
             sp.add_argument("--key", default=None, help="array name inside an .npz")
@@ -108,7 +110,7 @@ def main(argv=None) -> int:
     api.load()
     if not torch.cuda.is_available():
         raise SystemExit("no GPU: the fits run on the library's kernels only")
-    kw = dict(kkt_tol=a.kkt_tol, precision=a.precision, relax=a.relax)
+    kw = dict(kkt_tol=a.kkt_tol, precision=a.precision, relax=a.relax, rho=a.rho)
     if a.cmd == "var":
         s = load_series(a.series, a.key, order=a.order, time_axis=a.time_axis)
         lam = lambda_grid(_var_lambda_max(s, a.order, a.intercept), a.q, a.ratio)

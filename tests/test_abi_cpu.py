@@ -57,7 +57,8 @@ def _fit(api, lam, **kw):
     ([float("nan")], {}, "finite"),
     ([1.0], {"B1": 0}, "B1"),
     ([1.0], {"B2": 0}, "B2"),
-    ([1.0], {"rho": 0.0}, "rho"),
+    ([1.0], {"rho": -1.0}, "rho"),
+    ([1.0], {"rho": float("nan")}, "rho"),
     ([1.0], {"kkt_tol": -1.0}, "kkt_tol"),
     ([1.0], {"max_iter": 0}, "max_iter"),
     ([1.0], {"check_every": 0}, "check_every"),
@@ -67,6 +68,17 @@ def test_invalid_options_rejected_before_device_work(api, lam, kw, msg):
     code, err = _fit(api, lam, **kw)
     assert code == api.UOI_EINVAL
     assert msg in err
+
+
+def test_data_scaled_rho_not_allocation_free(api):
+    """rho = 0 reads the data's scale back through pinned host memory, so the
+    allocation-free entry point refuses it before any device work."""
+    o, keep = api.make_opts([1.0], rho=0.0, stream=None)
+    fake = C.c_void_p(0x1000)
+    lib = api.load()
+    code = lib.uoi_lasso_solve_batch_noalloc(2, 3, fake, fake, C.byref(o), None, None, fake, None, None, None)
+    assert code == api.UOI_EINVAL
+    assert "rho > 0" in lib.uoi_last_error().decode()
 
 
 def test_empty_lambda_grid_rejected(api):

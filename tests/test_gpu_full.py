@@ -99,13 +99,16 @@ def test_lasso_benchmark_setting_sampled(api, orc, precision):
 
 # --------------------------------------------------------------------------- VAR
 
-def test_var_p192_T10000_whole_fit(api, orc):
+@pytest.mark.parametrize("rho", [1.0, 0.0])
+def test_var_p192_T10000_whole_fit(api, orc, rho):
+    """rho = 0 (the penalty scaled to the data) reaches the same minimisers, so
+    the same expected values hold."""
     g = gold("var_p192_T10000.npz")
     pr = synth.var_small(0)
     p = pr.series.shape[1]
-    print("var p192 T10000 fp64 kkt 1e-10", flush=True)
+    print(f"var p192 T10000 fp64 kkt 1e-10 rho {rho}", flush=True)
     out = api.var_fit(cuda(pr.series), pr.lambdas, pr.B1, pr.B2, 0, kkt_tol=1e-10, precision="fp64",
-                      relax=1.8)
+                      relax=1.8, rho=rho)
     assert out["status"] == 0 and out["n_unconverged"] == 0
     got = words_to_bool(out["supports"].cpu().numpy(), p)
     want = words_to_bool(g["supports"], p)
@@ -116,16 +119,17 @@ def test_var_p192_T10000_whole_fit(api, orc):
     assert float(out["mu"].abs().max()) == 0.0
 
 
-def test_var_p1000_T20000_sampled(api, orc):
+@pytest.mark.parametrize("rho", [1.0, 0.0])
+def test_var_p1000_T20000_sampled(api, orc, rho):
     g = gold("var_p1000_T20000_sampled.npz")
     pr = synth.var_large(0)
     T, p = pr.series.shape
     N = T - 1
     L = orc.var_block_len(N)
     eqs = g["eqs"]
-    print("var p1000 T20000 fp64 kkt 1e-10 (400,000 selection solves)", flush=True)
+    print(f"var p1000 T20000 fp64 kkt 1e-10 (400,000 selection solves) rho {rho}", flush=True)
     out = api.var_fit(cuda(pr.series), pr.lambdas, pr.B1, pr.B2, 0, kkt_tol=1e-10, precision="fp64",
-                      relax=1.8)
+                      relax=1.8, rho=rho)
     assert out["status"] == 0 and out["n_unconverged"] == 0
     supp = out["supports"].cpu().numpy()                      # [q][p][W]
     got = words_to_bool(supp[:, eqs, :], p)                     # [q][neq][p]

@@ -46,15 +46,18 @@ def lasso_decided(orc, pr, seed, sel_beta):
     return all_dec | some_zero
 
 
-@pytest.mark.parametrize("precision,solver", [("fp64", "batched"), ("fp64", "plain"),
-                                              ("mixed", "batched")])
-def test_uoi_lasso_small_config(api, orc, precision, solver):
+@pytest.mark.parametrize("precision,solver,rho", [("fp64", "batched", 1.0), ("fp64", "plain", 1.0),
+                                                  ("mixed", "batched", 1.0), ("mixed", "batched", 0.0),
+                                                  ("fp64", "plain", 0.0)])
+def test_uoi_lasso_small_config(api, orc, precision, solver, rho):
+    """rho = 0 sets the penalty to the mean diagonal of the Grams; the
+    minimisers, hence every comparison, are the same."""
     pr = synth.lasso_small(0)
     seed = 0
     ref = orc.uoi_lasso(pr.X, pr.y, pr.lambdas, pr.B1, pr.B2, seed, keep_selection=True)
     assert ref["status"] == 0
     out = api.lasso_fit(cuda(pr.X), cuda(pr.y), pr.lambdas, pr.B1, pr.B2, seed, kkt_tol=1e-10,
-                        precision=precision, solver=solver, sel_beta=True)
+                        precision=precision, solver=solver, sel_beta=True, rho=rho)
     assert out["status"] == 0 and out["n_unconverged"] == 0
     p = pr.X.shape[1]
     dec = lasso_decided(orc, pr, seed, ref["sel_beta"])
