@@ -1039,6 +1039,8 @@ __global__ __launch_bounds__(256) void k_mean_diag(int nb, int p, const double *
 // is about 1; on a VAR series it is the series' mean square, where rho = 1 is
 // far too small for the spectrum and ADMM converges many times more slowly.
 // Falls back to 1 for an all-zero design.
+constexpr int kPinnedScalar = kPinnedLarge + 1;  // a pinned slot of its own
+
 double data_scaled_rho(hipStream_t s, int nb, int p, const double *G) {
     double *h = (double *)pinned_slot(kPinnedScalar, sizeof(double));
     hipLaunchKernelGGL(k_mean_diag, dim3(1), dim3(256), 0, s, nb, p, G, h);

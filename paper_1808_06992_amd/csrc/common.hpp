@@ -66,7 +66,7 @@ void pool_release();
 // buffer per device, like the pool; calls that overlap on one device race).
 // Grow-only pinned host buffers per (device, slot); a slot's buffer is reused by
 // the next call that asks for it, so its contents live until then.
-enum { kPinnedCounts = 0, kPinnedLists = 1, kPinnedFlag = 2, kPinnedLarge = 3, kPinnedScalar = 4 };
+enum { kPinnedCounts = 0, kPinnedLists = 1, kPinnedFlag = 2, kPinnedLarge = 3 };
 void *pinned_slot(int slot, size_t bytes);
 int *pinned_ints(size_t n);  // slot kPinnedCounts
 // A second stream of the current device (default priority, non-blocking) with
