@@ -55,6 +55,7 @@ struct GramArgs {
     int nfull;           // units 0..nfull-1 are whole tiles (batch-entry major)
     int fsplit;          // parts of each later tile (1: none split)
     double *part;        // raw partial tiles of the split units [unit - nfull][GT * GT]
+    int direct;          // rows of X are 16-byte aligned (X and ldx even): interior tiles load rows into LDS directly
 };
 
 // tile index within a batch entry -> tile coordinates (lower triangle, then C tiles)
@@ -98,31 +99,139 @@ __device__ __forceinline__ double aug_col(const GramArgs &g, size_t r, int j) {
     return 0.0;
 }
 
-// ROLE only names the instance (0: selection products of the bootstrap samples,
-// 1: estimation products), so kernel profiles keep the two apart.
-template <int ROLE, bool WGT>
-__global__ __launch_bounds__(256, 2) void k_gram_f64(GramArgs g) {
-    __shared__ double As[GK][GT];
-    __shared__ double Bs[GK][GT];
-    // unit -> (tile of batch entry b, part q of f)
-    const int u = blockIdx.x;
-    const int su = u - g.nfull;                      // index among split units, or < 0
-    const int f = su < 0 ? 1 : g.fsplit;
-    const int q = su < 0 ? 0 : su % f;
-    const int lt = su < 0 ? u : g.nfull + su / f;
-    const int b = lt / g.tiles;
-    int ti, tj;
+// A unit of work: one tile (or one part of a split tile) of batch entry b.
+struct GramUnit {
+    int b, i0, j0, mb, su, c0, c1;  // rows of chunks [c0, c1) of GK rows
     bool isC;
-    tile_coords(g, lt % g.tiles, ti, tj, isC);
-    const int i0 = ti * GT, j0 = tj * GT;
-    const int mb = g.mcount ? g.mcount[b] : g.m;
+};
+
+// The accumulators of a wave (a 64x64 quadrant) after the unit's rows: stored
+// divided by the row count, or as raw parts of a split tile.
+__device__ __forceinline__ void gram_finish(const GramArgs &g, const GramUnit &t, const dx4 (&acc)[4][4]) {
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int wm = wid >> 1, wn = wid & 1, lr = lane & 15, lk = lane >> 4;
+    if (t.su >= 0) {  // a part of a split tile: raw accumulators, in register order
+        double *P = g.part + (size_t)t.su * GT * GT;
+#pragma unroll
+        for (int fm = 0; fm < 4; ++fm)
+#pragma unroll
+            for (int fn = 0; fn < 4; ++fn)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) P[((((wid * 4 + fm) * 4 + fn) * 4 + e) << 6) + lane] = acc[fm][fn][e];
+        return;
+    }
+    const double inv = 1.0 / (double)(g.div > 0 ? g.div : t.mb);
+#pragma unroll
+    for (int fm = 0; fm < 4; ++fm)
+#pragma unroll
+        for (int fn = 0; fn < 4; ++fn)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                gram_store(g, t.b, t.i0 + wm * 64 + fm * 16 + mfma_row(0.0, lk, e), t.j0 + wn * 64 + fn * 16 + lr,
+                           t.isC, acc[fm][fn][e] * inv);
+}
+
+// One chunk of GK staged rows: acc += A_chunk' B_chunk, the A rows scaled by
+// wrow (per staged row, from LDS) when W.
+template <bool W>
+__device__ __forceinline__ void gram_mma(const double (*As)[GT], const double (*Bs)[GT], const double *wrow,
+                                         dx4 (&acc)[4][4]) {
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int wm = wid >> 1, wn = wid & 1, lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int s = 0; s < GK / 4; ++s) {
+        double av[4], bv[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) av[a] = As[4 * s + lk][wm * 64 + 16 * a + lr];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) bv[a] = Bs[4 * s + lk][wn * 64 + 16 * a + lr];
+        if (W) {
+            const double ws = wrow[4 * s + lk];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) av[a] *= ws;
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[a][q] = mfma16x16x4(av[a], bv[q], acc[a][q]);
+    }
+}
+
+// Interior tiles (every column of both sides a design column, rows of X 16-byte
+// aligned): rows go from memory straight into LDS (16 bytes per lane, a wave
+// fills one 128-column row of one side per instruction), two LDS buffers, one
+// barrier per chunk.  Wave w stages rows 4w .. 4w+3 of each chunk; their indices
+// and multipliers are loaded a chunk ahead by lanes 0-3 and taken into scalar
+// registers, so a row's address is scalar arithmetic plus the lane's fixed
+// 16-byte column offset.  The multiplier (weight, or 1; 0 for rows past the
+// sample, which read row 0) scales the A values as they are read from LDS.
+template <bool WGT>
+__device__ __forceinline__ void gram_tile_direct(const GramArgs &g, const GramUnit &t, double (*As)[GK][GT],
+                                                 double (*Bs)[GK][GT], double (*Ws)[GK]) {
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane((int)(tid >> 6));
+    const int32_t *rb = g.rows + (size_t)t.b * g.m;
+    const int32_t *wb = WGT ? g.wt + (size_t)t.b * g.m : nullptr;
+    const int mb = t.mb;
+    const double *xa = g.X + t.i0 + 2 * lane, *xb = g.X + t.j0 + 2 * lane;
+    dx4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = dx4{0, 0, 0, 0};
+    // lanes 0-3 (and copies in the other lanes): index and multiplier of row
+    // 4w + (lane & 3) of chunk c
+    auto load_rows = [&](int c, int &vi, int &vw) {
+        const int k = c * GK + 4 * w + (lane & 3);
+        const int kc = k < mb ? k : 0;
+        vi = rb[kc];
+        const int wk = WGT ? wb[kc] : 1;  // loaded unconditionally (no branch around a load)
+        vw = k < mb ? wk : 0;
+    };
+    // rows of chunk c (indices vi, multipliers vw) into buffer buf
+    auto stage = [&](int buf, int vi, int vw) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const size_t row = (size_t)__builtin_amdgcn_readlane(vi, r) * g.ldx;
+            __builtin_amdgcn_global_load_lds((const void *)(xa + row),
+                                             (__attribute__((address_space(3))) void *)&As[buf][4 * w + r][0], 16, 0,
+                                             0);
+            __builtin_amdgcn_global_load_lds((const void *)(xb + row),
+                                             (__attribute__((address_space(3))) void *)&Bs[buf][4 * w + r][0], 16, 0,
+                                             0);
+        }
+        if (lane < 4) Ws[buf][4 * w + lane] = (double)vw;
+    };
+    int vi, vw, ni, nw;
+    load_rows(t.c0, vi, vw);
+    stage(t.c0 & 1, vi, vw);
+    load_rows(t.c0 + 1, ni, nw);
+    for (int c = t.c0; c < t.c1; ++c) {
+        const int buf = c & 1;
+        // this wave's copies into buffer buf (and every earlier load) complete,
+        // then every wave's: the barrier also ends all reads of buffer buf ^ 1
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (c + 1 < t.c1) {
+            stage(buf ^ 1, ni, nw);
+            load_rows(c + 2, ni, nw);
+        }
+        gram_mma<true>(As[buf], Bs[buf], Ws[buf], acc);
+    }
+    gram_finish(g, t, acc);
+}
+
+// Other tiles: each thread stages one column of 8 rows per chunk through
+// registers, the values of the next chunk in flight while the current one is
+// multiplied.
+template <bool WGT>
+__device__ __forceinline__ void gram_tile_staged(const GramArgs &g, const GramUnit &t, double (*As)[GT],
+                                                 double (*Bs)[GT]) {
+    const int b = t.b, i0 = t.i0, j0 = t.j0, mb = t.mb;
+    const bool isC = t.isC;
     const int32_t *rb = g.rows + (size_t)b * g.m;
     const int naug = g.p + g.pa;
-
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wid = tid >> 6;
-    const int wm = wid >> 1, wn = wid & 1;
-    const int lr = lane & 15, lk = lane >> 4;
     // this thread stages rows kk = (tid >> 7) + 2q, column cc = tid & 127
     const int kk0 = tid >> 7, cc = tid & 127;
     const int ia = i0 + cc, jb = j0 + cc;
@@ -182,8 +291,7 @@ __global__ __launch_bounds__(256, 2) void k_gram_f64(GramArgs g) {
     };
 
     // this unit's chunks of GK rows: [c0, c1)
-    const int nchunk = (mb + GK - 1) / GK;
-    const int c0 = (int)((int64_t)q * nchunk / f), c1 = (int)((int64_t)(q + 1) * nchunk / f);
+    const int c0 = t.c0, c1 = t.c1;
     load_idx(c0 * GK, idx1, wi1);
     load_val(c0 * GK, idx1);
     store(wi1);
@@ -195,18 +303,7 @@ __global__ __launch_bounds__(256, 2) void k_gram_f64(GramArgs g) {
             load_val((c + 1) * GK, idx1);        // values of chunk c+1
             load_idx((c + 2) * GK, idx2, wi2);   // indices and weights of chunk c+2
         }
-#pragma unroll
-        for (int s = 0; s < GK / 4; ++s) {
-            double av[4], bv[4];
-#pragma unroll
-            for (int a = 0; a < 4; ++a) av[a] = As[4 * s + lk][wm * 64 + 16 * a + lr];
-#pragma unroll
-            for (int a = 0; a < 4; ++a) bv[a] = Bs[4 * s + lk][wn * 64 + 16 * a + lr];
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) acc[a][q] = mfma16x16x4(av[a], bv[q], acc[a][q]);
-        }
+        gram_mma<false>(As, Bs, nullptr, acc);
         __syncthreads();
         if (more) {
             store(wi1);
@@ -219,25 +316,38 @@ __global__ __launch_bounds__(256, 2) void k_gram_f64(GramArgs g) {
         __syncthreads();
     }
 
-    if (su >= 0) {  // a part of a split tile: raw accumulators, in register order
-        double *P = g.part + (size_t)su * GT * GT;
-#pragma unroll
-        for (int fm = 0; fm < 4; ++fm)
-#pragma unroll
-            for (int fn = 0; fn < 4; ++fn)
-#pragma unroll
-                for (int t = 0; t < 4; ++t) P[((((wid * 4 + fm) * 4 + fn) * 4 + t) << 6) + lane] = acc[fm][fn][t];
-        return;
-    }
-    const double inv = 1.0 / (double)(g.div > 0 ? g.div : mb);
-#pragma unroll
-    for (int fm = 0; fm < 4; ++fm)
-#pragma unroll
-        for (int fn = 0; fn < 4; ++fn)
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-                gram_store(g, b, i0 + wm * 64 + fm * 16 + mfma_row(0.0, lk, t), j0 + wn * 64 + fn * 16 + lr, isC,
-                           acc[fm][fn][t] * inv);
+    gram_finish(g, t, acc);
+}
+
+// ROLE only names the instance (0: selection products of the bootstrap samples,
+// 1: estimation products), so kernel profiles keep the two apart.
+template <int ROLE, bool WGT>
+__global__ __launch_bounds__(256, 2) void k_gram_f64(GramArgs g) {
+    __shared__ double As[2][GK][GT];
+    __shared__ double Bs[2][GK][GT];
+    __shared__ double Ws[2][GK];
+    // unit -> (tile of batch entry b, part q of f)
+    const int u = blockIdx.x;
+    const int su = u - g.nfull;                      // index among split units, or < 0
+    const int f = su < 0 ? 1 : g.fsplit;
+    const int q = su < 0 ? 0 : su % f;
+    const int lt = su < 0 ? u : g.nfull + su / f;
+    GramUnit t;
+    t.b = lt / g.tiles;
+    t.su = su;
+    int ti, tj;
+    tile_coords(g, lt % g.tiles, ti, tj, t.isC);
+    t.i0 = ti * GT;
+    t.j0 = tj * GT;
+    t.mb = g.mcount ? g.mcount[t.b] : g.m;
+    const int nchunk = (t.mb + GK - 1) / GK;
+    t.c0 = (int)((int64_t)q * nchunk / f);
+    t.c1 = (int)((int64_t)(q + 1) * nchunk / f);
+    const bool direct = g.direct && !t.isC && t.i0 + GT <= g.p && t.j0 + GT <= g.p;
+    if (direct)
+        gram_tile_direct<WGT>(g, t, As, Bs, Ws);
+    else
+        gram_tile_staged<WGT>(g, t, As[0], Bs[0]);
 }
 
 // Split tiles: the sum of their parts in part order, divided by the row count.
@@ -411,6 +521,7 @@ void launch_gram_f64(hipStream_t s, int nb, int m, const int32_t *rows, const in
     GramArgs g{};
     g.m = m; g.rows = rows; g.mcount = mcount; g.p = p; g.X = X; g.ldx = ldx;
     g.Y = Y; g.ldy = ldy; g.G = G; g.C = C; g.ss = ss;
+    g.direct = ldx % 2 == 0 && ((uintptr_t)X & 15) == 0;
     const GramPlan pl = gram_plan(nb, m, p, pe, C != nullptr, gram_slots_of(role, false));
     run_gram(s, g, pl, role, false, part, part_bytes);
 }
@@ -422,6 +533,7 @@ void launch_gram_f64_weighted(hipStream_t s, int nb, int m, const int32_t *rows,
     GramArgs g{};
     g.m = m; g.rows = rows; g.mcount = mcount; g.p = p; g.X = X; g.ldx = ldx;
     g.Y = Y; g.ldy = ldy; g.G = G; g.C = C; g.ss = ss; g.wt = w; g.div = div;
+    g.direct = ldx % 2 == 0 && ((uintptr_t)X & 15) == 0;
     const GramPlan pl = gram_plan(nb, m, p, pe, C != nullptr, gram_slots_of(0, true));
     run_gram(s, g, pl, 0, true, part, part_bytes);
 }
