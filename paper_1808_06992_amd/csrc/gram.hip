@@ -11,11 +11,14 @@
 // response columns (VAR) get their own rectangular tiles instead.
 //
 // Work decomposition: 128x128 output tiles of the lower triangle (plus C
-// tiles).  A tile streams the sampled rows in chunks of 16 through LDS: the
-// next chunk's gathered values are loaded into registers while the current
-// chunk is multiplied, and the row indices two chunks ahead, so the index ->
-// value dependency never stalls the MFMAs.  4 waves each own a 64x64 quadrant
-// as 4x4 MFMA 16x16x4 blocks.
+// tiles), dealt XCD by XCD so that the tiles of one batch entry share an L2.
+// A tile streams the sampled rows in chunks of 16 through LDS; 4 waves each own
+// a 64x64 quadrant as 4x4 MFMA 16x16x4 blocks.  Interior tiles (all columns
+// design columns) copy each gathered row segment from memory straight into LDS,
+// 16 bytes per lane, into two alternating buffers.  Tiles that reach past the
+// last design column stage through registers: the next chunk's gathered values
+// are loaded while the current chunk is multiplied, and the row indices two
+// chunks ahead, so the index -> value dependency never stalls the MFMAs.
 //
 // Short launches: with S workgroup slots on the chip (CUs x resident workgroups
 // per CU) and U < S tiles (the estimation products over the union's columns,
