@@ -21,7 +21,9 @@ carries
   workgroup, float64), batched float64, batched mixed, each with and without
   ADMM over-relaxation, and the mixed sweep started by the learned network;
 * the error of every variant against the CPU oracle on the bootstraps the
-  oracle sample shares with the GPU run, and the oracle's own throughput.
+  oracle sample shares with the GPU run, and the oracle's own throughput;
+* UoI_VAR fits of the two VAR workloads (p192 T10000, p1000 T20000), with the
+  ADMM penalty rho = 1 and scaled to the data (--no-var skips them).
 
 Profiling helpers (no GPU needed):  --summarize-trace DIR and
 --summarize-pmc DIR print the text summaries kept under profiles/ from
@@ -77,6 +79,8 @@ def parse():
     ap.add_argument("--no-compare", action="store_true", help="skip the other variants")
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned warm-start variant")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-var", action="store_true",
+                    help="skip the UoI_VAR fits (p192 T10000 and p1000 T20000, rho 1 and rho scaled to the data)")
     ap.add_argument("--cpu-boots", type=int, default=48,
                     help="bootstraps of the CPU oracle sample (B1 = B2 = this)")
     ap.add_argument("--mlp-seeds", type=int, default=4, help="design seeds of the network's training set")
@@ -330,6 +334,34 @@ def make_traffic(slot, fetch_dir, write_dir):
 
 # --------------------------------------------------------------------------- main
 
+def var_fits(api, torch, synth, log):
+    """UoI_VAR fits of the two VAR workloads (mixed, relax 1.8, KKT 1e-6): one
+    warm-up and one timed fit each, with the paper's rho = 1 and with rho scaled
+    to the data (rho = 0: the mean diagonal of the Grams).  A selection solve is
+    one (bootstrap, lambda, equation) LASSO of dimension p."""
+    out = {}
+    for name, mk in (("var_p192_T10000", synth.var_small), ("var_p1000_T20000", synth.var_large)):
+        pr = mk(0)
+        s = torch.as_tensor(pr.series).cuda()
+        nsol = pr.B1 * pr.lambdas.size * pr.series.shape[1]
+        res = {"B1": pr.B1, "q": int(pr.lambdas.size), "B2": pr.B2, "selection_solves": nsol}
+        for label, rho in (("rho_1", 1.0), ("rho_data", 0.0)):
+            kw = dict(kkt_tol=1e-6, precision="mixed", relax=1.8, rho=rho)
+            api.var_fit(s, pr.lambdas, pr.B1, pr.B2, 0, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            o = api.var_fit(s, pr.lambdas, pr.B1, pr.B2, 0, **kw)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            it = o["iters"].float()
+            res[label] = dict(ms_per_fit=round(1000 * t, 2), solves_per_s=round(nsol / t, 1),
+                              mean_iters=round(float(it.mean()), 2), max_iters=int(it.max()),
+                              unconverged=int(o["n_unconverged"]), status=int(o["status"]))
+            log(f"{name} {label}: {1000 * t:.1f} ms/fit, {nsol / t:.0f} solves/s, mean iters {float(it.mean()):.1f}")
+        out[name] = res
+    return out
+
+
 def main():
     a = parse()
     if a.summarize_trace:
@@ -436,6 +468,11 @@ def main():
     for ref in ("plain", "plain_relaxed"):
         if compare.get(ref, {}).get("solves_per_s"):
             line["vs_" + ref] = round(head["solves_per_s"] / compare[ref]["solves_per_s"], 2)
+    if not a.no_var:
+        try:
+            line["var"] = var_fits(api, torch, synth, log)
+        except Exception as e:  # reported, never hidden
+            line["var"] = dict(error=f"{type(e).__name__}: {e}")
     if not a.no_cpu:
         boots = min(a.cpu_boots, pr.B1)
         base, orc = cpu_baseline(pr, boots)
