@@ -25,6 +25,24 @@
 
 namespace uoi {
 
+// Logical (column tile x, row tile y, matrix z) of a product workgroup.  z is
+// slowest, so the tiles of one matrix stay on one XCD (xcd_remap), and y is
+// fastest: the workgroups resident together on an XCD then cover a few column
+// strips of V over every row strip of A.  A column strip of V is fetched from
+// beyond the L2 about once per product, and A (far smaller than V when there
+// are many columns) is the operand that is fetched again.  With x fastest, the
+// strips of V were fetched once per row tile.
+__device__ __forceinline__ void bg_tile(int &x, int &y, int &z) {
+    const int gx = gridDim.x, gy = gridDim.y;
+    const int total = gx * gy * gridDim.z;
+    const int L = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const int id = xcd_remap(L, total);
+    z = id / (gx * gy);
+    const int rem = id - z * gx * gy;
+    x = rem / gy;
+    y = rem - x * gy;
+}
+
 template <typename T>
 struct AccT {
     typedef typename std::conditional<std::is_same<T, double>::value, dx4, fx4>::type type;
@@ -39,7 +57,7 @@ __global__ __launch_bounds__(256) void k_bgemm(int p, int R, const T *__restrict
     constexpr int TN = 16 * FN;
     __shared__ T Vs[2][BG_KC][TN];
     int bx, by, b;
-    xcd_tile(bx, by, b);
+    bg_tile(bx, by, b);
     const int r0 = bx * TN;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wid = tid >> 6;
@@ -195,7 +213,7 @@ __global__ __launch_bounds__(256) void k_bgemm_bf3(int p, int R, const float *__
     constexpr int KP = KC + 8;  // k stride of an LDS plane row (bfloat16), 16-byte aligned
     __shared__ __attribute__((aligned(16))) __bf16 Vs[2][3][TN][KP];
     int bx, by, b;
-    xcd_tile(bx, by, b);
+    bg_tile(bx, by, b);
     const int r0 = bx * TN;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wid = tid >> 6;

@@ -151,17 +151,6 @@ __device__ __forceinline__ int xcd_remap(int L, int total) {
     const int x = L % kNumXcd, s = L / kNumXcd;
     return x * q + min(x, r) + s;
 }
-// (x, y, z) of the logical workgroup, z slowest: tiles of one z stay on one XCD.
-__device__ __forceinline__ void xcd_tile(int &x, int &y, int &z) {
-    const int gx = gridDim.x, gy = gridDim.y;
-    const int total = gx * gy * gridDim.z;
-    const int L = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
-    const int id = xcd_remap(L, total);
-    z = id / (gx * gy);
-    const int rem = id - z * gx * gy;
-    y = rem / gx;
-    x = rem - y * gx;
-}
 
 __device__ __forceinline__ double soft_threshold(double a, double t) {
     return a > t ? a - t : (a < -t ? a + t : 0.0);
