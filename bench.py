@@ -117,11 +117,11 @@ def sources_digest(files):
     return h.hexdigest()[:16]
 
 
-def stored_traffic(slot):
+def stored_traffic(slot, workload=WORKLOAD):
     """Per-launch HBM bytes of the slot's kernel from the committed counter
     summary, or None when absent or taken on other sources."""
     name, files = KERNELS[slot]
-    path = os.path.join(ROOT, "profiles", f"traffic_{slot}_{WORKLOAD}.txt")
+    path = os.path.join(ROOT, "profiles", f"traffic_{slot}_{workload}.txt")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -178,8 +178,9 @@ def selection_betas(api, X, y, pr, kw, mlp=None):
     return out["sel_beta"].cpu().numpy(), out["beta"].cpu().numpy()
 
 
-def roofline(kst):
-    """Dominant kernel = the timed kernel slot with the largest device time."""
+def roofline(kst, workload=WORKLOAD):
+    """Dominant kernel = the timed kernel slot with the largest device time.  Its
+    HBM traffic comes from the workload's committed counter summary, if any."""
     cands = {k: v for k, v in kst.items() if v["launches"] > 0}
     dom = max(cands, key=lambda k: cands[k]["ms"])
     k = cands[dom]
@@ -196,7 +197,7 @@ def roofline(kst):
         r = dict(bound="mfma", achieved=round(tfl, 2), peak=PEAK_TFLOPS[dt], unit="TFLOP/s",
                  frac=round(tfl / PEAK_TFLOPS[dt], 4))
     launches = max(int(k["launches"]), 1)
-    r.update(traffic=stored_traffic(dom), kernel=KERNELS[dom][0], slot=dom, launches=int(k["launches"]),
+    r.update(traffic=stored_traffic(dom, workload), kernel=KERNELS[dom][0], slot=dom, launches=int(k["launches"]),
              avg_launch_us=round(1000.0 * k["ms"] / launches, 2),
              algorithmic_bytes_per_launch=round(k["bytes"] / launches),
              algorithmic_flops_per_launch=round(k["flops"] / launches),
@@ -338,7 +339,9 @@ def var_fits(api, torch, synth, log):
     """UoI_VAR fits of the two VAR workloads (mixed, relax 1.8, KKT 1e-6): one
     warm-up and one timed fit each, with the paper's rho = 1 and with rho scaled
     to the data (rho = 0: the mean diagonal of the Grams).  A selection solve is
-    one (bootstrap, lambda, equation) LASSO of dimension p."""
+    one (bootstrap, lambda, equation) LASSO of dimension p.  Each timed fit also
+    reports its stage times and the roofline object of its dominant kernel (per
+    launch averages over the fit's launches, partly active ones included)."""
     out = {}
     for name, mk in (("var_p192_T10000", synth.var_small), ("var_p1000_T20000", synth.var_large)):
         pr = mk(0)
@@ -346,7 +349,7 @@ def var_fits(api, torch, synth, log):
         nsol = pr.B1 * pr.lambdas.size * pr.series.shape[1]
         res = {"B1": pr.B1, "q": int(pr.lambdas.size), "B2": pr.B2, "selection_solves": nsol}
         for label, rho in (("rho_1", 1.0), ("rho_data", 0.0)):
-            kw = dict(kkt_tol=1e-6, precision="mixed", relax=1.8, rho=rho)
+            kw = dict(kkt_tol=1e-6, precision="mixed", relax=1.8, rho=rho, timing=True)
             api.var_fit(s, pr.lambdas, pr.B1, pr.B2, 0, **kw)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -356,7 +359,9 @@ def var_fits(api, torch, synth, log):
             it = o["iters"].float()
             res[label] = dict(ms_per_fit=round(1000 * t, 2), solves_per_s=round(nsol / t, 1),
                               mean_iters=round(float(it.mean()), 2), max_iters=int(it.max()),
-                              unconverged=int(o["n_unconverged"]), status=int(o["status"]))
+                              unconverged=int(o["n_unconverged"]), status=int(o["status"]),
+                              stage_ms={k: round(v, 3) for k, v in o["stage_ms"].items()},
+                              roofline=roofline(o["kstat"], name))
             log(f"{name} {label}: {1000 * t:.1f} ms/fit, {nsol / t:.0f} solves/s, mean iters {float(it.mean()):.1f}")
         out[name] = res
     return out
