@@ -778,11 +778,17 @@ struct AdmmWork {
     // float32 phase
     float *M32, *h32, *z32, *u32;
     __bf16 *vp0, *vp1;  // float32 phase: v as bfloat16 planes [nb][3][R][ldk]
+    int fm32;           // row blocks per wave of the float32 product (1 or 2)
     double *z64tmp;
 };
 
+// Products with more than one column tile may take two row blocks per wave
+// (the autotuner times both).
+inline bool offer_fm2(const AdmmProblem &P) { return P.R > 64 && P.p > 64; }
+
 AdmmWork carve(const AdmmProblem &P, int precision, int solver, Arena &ar) {
     AdmmWork w{};
+    w.fm32 = 1;
     size_t np2 = (size_t)P.nb * P.p * P.p, nst = (size_t)P.nb * P.p * P.R;
     w.M = ar.take<double>(np2);
     w.h = ar.take<double>((size_t)P.nb * P.p * P.pe);
@@ -919,7 +925,8 @@ static int sweep(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T
                     AdmmEpiBf3<FN> epi{h, z, u, pout, w.state, P.lam, P.p, P.R, P.pe, bf3_ldk(P.p),
                                        (float)P.rho, (float)(1.0 / P.rho), (float)P.relax,
                                        t == n - 1 ? w.vmax : nullptr, w.rmax};
-                    run_bgemm_bf3<FN>(st, P.nb, P.p, P.R, M, pin, epi);
+                    if (w.fm32 == 2) run_bgemm_bf3<FN, 2>(st, P.nb, P.p, P.R, M, pin, epi);
+                    else run_bgemm_bf3<FN, 1>(st, P.nb, P.p, P.R, M, pin, epi);
                 } else {
                     AdmmEpi<T, 1, FN> epi{h, z, u, vout, w.state, P.lam, P.p, P.R, P.pe, (T)P.rho,
                                           (T)(1.0 / P.rho), (T)P.relax};
@@ -938,7 +945,7 @@ static int sweep(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T
             GraphKey key;
             key.add(sizeof(T)).add(par).add(n).add(P.fn32).add(P.fn64).add(P.nb).add(P.p).add(P.R).add(P.pe)
                 .add(M).add(h).add(z)
-                .add(u).add(va).add(vb).add(w.vp0).add(w.vp1).add(w.state).add(P.lam).add(w.vmax).add(w.rmax)
+                .add(u).add(va).add(vb).add(w.vp0).add(w.vp1).add(w.fm32).add(w.state).add(P.lam).add(w.vmax).add(w.rmax)
                 .add(P.rho).add(P.relax);
             graph_launch(s, key, [&](hipStream_t cs) { issue(cs, par, n); });
         } else {
@@ -1168,8 +1175,11 @@ void admm_solve(hipStream_t s, const AdmmProblem &P0, int precision, int solver,
     // fused multiply-adds), are the same for every width, so the autotuner times
     // them on the live operands: the float32 iteration with its real epilogue
     // writing a scratch copy of the state, the float64 one as the bare product.
+    // With more than one column tile, the float32 candidates come twice: one row
+    // block per wave (candidates 0 .. n - 1), then two (n .. 2n - 1; the same
+    // accumulation order, so the same results).  The choice sets w.fm32.
     auto pick_fn = [&](bool f32) -> int {
-        std::vector<int> cand;
+        std::vector<int> cand, fm;
         for (int f = 1; f <= 4; ++f) {
             const long tf = cdiv(P.R, 16 * f), wf = tf * 16 * f - P.R;
             bool dominated = false;
@@ -1179,10 +1189,22 @@ void admm_solve(hipStream_t s, const AdmmProblem &P0, int precision, int solver,
             }
             if (!dominated) cand.push_back(f);
         }
+        fm.assign(cand.size(), 1);
+        if (f32 && offer_fm2(P)) {
+            const size_t n0 = cand.size();
+            for (size_t c = 0; c < n0; ++c) {
+                cand.push_back(cand[c]);
+                fm.push_back(2);
+            }
+        }
         const std::string key = std::string(f32 ? "admm32_fn" : "admm64_fn") + "/nb" + std::to_string(P.nb) +
                                 "/p" + std::to_string(P.p) + "/R" + std::to_string(P.R);
         const int nc = (int)cand.size();
-        if (!P.tune || nc == 1) return cand[std::min(std::max(tune_lookup(key, 0), 0), nc - 1)];
+        auto chosen = [&](int c) {
+            if (f32) w.fm32 = fm[c];
+            return cand[c];
+        };
+        if (!P.tune || nc == 1) return chosen(std::min(std::max(tune_lookup(key, 0), 0), nc - 1));
         const size_t nst_ = (size_t)P.nb * P.p * P.R;
         const TuneResult r = tune_choose(s, key, nc, [&](int c) {
             UOI_DISPATCH_FN_RT(cand[c], {
@@ -1192,14 +1214,15 @@ void admm_solve(hipStream_t s, const AdmmProblem &P0, int precision, int solver,
                     float *zs = (float *)w.v0, *us = (float *)w.v0 + nst_;
                     AdmmEpiBf3<FN> e{w.h32, zs, us, w.vp1, w.state, P.lam, P.p, P.R, P.pe, bf3_ldk(P.p),
                                      (float)P.rho, (float)(1.0 / P.rho), (float)P.relax, nullptr, w.rmax};
-                    run_bgemm_bf3<FN>(s, P.nb, P.p, P.R, w.M32, w.vp0, e);
+                    if (fm[c] == 2) run_bgemm_bf3<FN, 2>(s, P.nb, P.p, P.R, w.M32, w.vp0, e);
+                    else run_bgemm_bf3<FN, 1>(s, P.nb, P.p, P.R, w.M32, w.vp0, e);
                 } else {
                     StoreEpi<double, 1, FN> e{w.v1, P.p, P.R};
                     run_bgemm<double, 1, FN>(s, P.nb, P.p, P.R, w.M, out.z, e);
                 }
             });
         }, 5);
-        return cand[r.choice];
+        return chosen(r.choice);
     };
     int it = 0, active = 0;
     if (solver == UOI_SOLVER_PLAIN) {

@@ -205,8 +205,13 @@ __device__ __forceinline__ fx4 mfma16x16x32(bfx8 a, bfx8 b, fx4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-template <int FN, bool VEC4, class Epi>
-__global__ __launch_bounds__(256) void k_bgemm_bf3(int p, int R, const float *__restrict__ A,
+// FM row blocks of 16 per wave (a workgroup covers 64 FM rows): with FM = 2 each
+// V operand read from LDS feeds twice the MFMAs and each V strip is fetched by
+// half as many workgroups.  Its register ring is two chunks deep and its
+// registers are held to three waves per SIMD (measured best of depths 2 to 4,
+// with and without the bound).
+template <int FN, int FM, bool VEC4, class Epi>
+__global__ __launch_bounds__(256, FM == 2 ? 3 : 1) void k_bgemm_bf3(int p, int R, const float *__restrict__ A,
                                                    const __bf16 *__restrict__ Vp, int ldk, Epi epi) {
     constexpr int TN = 16 * FN;
     constexpr int KC = BF3_KC;
@@ -217,14 +222,16 @@ __global__ __launch_bounds__(256) void k_bgemm_bf3(int p, int R, const float *__
     const int r0 = bx * TN;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wid = tid >> 6;
-    const int i_base = by * 64 + wid * 16;
+    const int i_base = by * (64 * FM) + wid * (16 * FM);
     const int lr = lane & 15, lk = lane >> 4;
     if (!epi.tile_active(b, r0, TN)) return;  // uniform over the workgroup
 
     const float *Ab = A + (size_t)b * p * p;
-    fx4 acc[1][FN];
+    fx4 acc[FM][1][FN];
 #pragma unroll
-    for (int c = 0; c < FN; ++c) acc[0][c] = fx4{0.f, 0.f, 0.f, 0.f};
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int c = 0; c < FN; ++c) acc[a][0][c] = fx4{0.f, 0.f, 0.f, 0.f};
 
     // All loads come from valid addresses: the V planes hold zeros at rows p ..
     // ldk - 1, which cancel the clamped A values they meet; rows of A past p and
@@ -232,12 +239,14 @@ __global__ __launch_bounds__(256) void k_bgemm_bf3(int p, int R, const float *__
     // The loop body has no branch around a load: the compiler can then keep the
     // loads of several chunks in flight (a load under a branch makes it wait for
     // every earlier one).
-    const float *arow = Ab + (size_t)min(i_base + lr, p - 1) * p;
+    const float *arows[FM];
+#pragma unroll
+    for (int a = 0; a < FM; ++a) arows[a] = Ab + (size_t)min(i_base + 16 * a + lr, p - 1) * p;
     // Lane group lk takes k = 4 lk .. 4 lk + 3 and 16 + 4 lk .. 16 + 4 lk + 3 of a
     // chunk (elements 0-3 and 4-7 of its MFMA operand), so that each of the two
     // loads covers 64 contiguous bytes of a row; V is laid out in LDS in the same
     // order.
-    auto load_a = [&](float (&an)[8], int k0) {
+    auto load_a = [&](float (&an)[8], const float *arow, int k0) {
         const int k = k0 + 4 * lk;
         if (VEC4) {  // rows of A 16-byte aligned (p % 4 == 0)
             const fx4 x0 = *(const fx4 *)(arow + min(k, p - 4));
@@ -286,18 +295,20 @@ __global__ __launch_bounds__(256) void k_bgemm_bf3(int p, int R, const float *__
     // chunks of work (the MFMAs alone are too short to cover it).  The chunk loop
     // is unrolled by D so that ring slots are static registers, and runs over a
     // multiple of D chunks: chunks past p are staged as zeros.
-    constexpr int D = BF3_D;
+    constexpr int D = FM == 2 ? 2 : BF3_D;  // (bf3_ldk pads for the deepest ring)
     const int nchunk = (p + KC - 1) / KC;
-    float an[D][8];
+    float an[D][FM][8];
     vraw vn[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
         load_v(vn[d], d * KC);
-        load_a(an[d], d * KC);
+#pragma unroll
+        for (int a = 0; a < FM; ++a) load_a(an[d][a], arows[a], d * KC);
     }
-    bfx8 a1, a2, a3;
+    bfx8 a1[FM], a2[FM], a3[FM];
     store_v(0, vn[0]);
-    split_bf16x3(an[0], a1, a2, a3);
+#pragma unroll
+    for (int a = 0; a < FM; ++a) split_bf16x3(an[0][a], a1[a], a2[a], a3[a]);
     __syncthreads();
     for (int c = 0; c < nchunk; c += D) {
 #pragma unroll
@@ -305,39 +316,46 @@ __global__ __launch_bounds__(256) void k_bgemm_bf3(int p, int R, const float *__
             const int cc = c + d;
             // slot d was staged at the end of the previous chunk
             load_v(vn[d], (cc + D) * KC);
-            load_a(an[d], (cc + D) * KC);
+#pragma unroll
+            for (int a = 0; a < FM; ++a) load_a(an[d][a], arows[a], (cc + D) * KC);
             const int cur = cc & 1;
 #pragma unroll
             for (int q = 0; q < FN; ++q) {
                 const bfx8 b1 = *(const bfx8 *)&Vs[cur][0][16 * q + lr][8 * lk];
                 const bfx8 b2 = *(const bfx8 *)&Vs[cur][1][16 * q + lr][8 * lk];
                 const bfx8 b3 = *(const bfx8 *)&Vs[cur][2][16 * q + lr][8 * lk];
-                fx4 t = acc[0][q];
-                t = mfma16x16x32(a3, b1, t);  // small terms first
-                t = mfma16x16x32(a2, b2, t);
-                t = mfma16x16x32(a1, b3, t);
-                t = mfma16x16x32(a2, b1, t);
-                t = mfma16x16x32(a1, b2, t);
-                acc[0][q] = mfma16x16x32(a1, b1, t);
+#pragma unroll
+                for (int a = 0; a < FM; ++a) {
+                    fx4 t = acc[a][0][q];
+                    t = mfma16x16x32(a3[a], b1, t);  // small terms first
+                    t = mfma16x16x32(a2[a], b2, t);
+                    t = mfma16x16x32(a1[a], b3, t);
+                    t = mfma16x16x32(a2[a], b1, t);
+                    t = mfma16x16x32(a1[a], b2, t);
+                    acc[a][0][q] = mfma16x16x32(a1[a], b1, t);
+                }
             }
             store_v(cur ^ 1, vn[(d + 1) % D]);
-            split_bf16x3(an[(d + 1) % D], a1, a2, a3);
+#pragma unroll
+            for (int a = 0; a < FM; ++a) split_bf16x3(an[(d + 1) % D][a], a1[a], a2[a], a3[a]);
             __syncthreads();
         }
     }
-    if (i_base < p) epi.apply(b, i_base, r0, lr, lk, acc);
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+        if (i_base + 16 * a < p) epi.apply(b, i_base + 16 * a, r0, lr, lk, acc[a]);
 }
 
 // Vp: three bfloat16 planes [nb][3][R][ldk], ldk = bf3_ldk(p), zero at rows >= p.
-template <int FN, class Epi>
+template <int FN, int FM = 1, class Epi>
 inline void run_bgemm_bf3(hipStream_t s, int nb, int p, int R, const float *A, const __bf16 *Vp,
                           const Epi &epi) {
-    dim3 grid(cdiv(R, 16 * FN), cdiv(p, 64), nb);
+    dim3 grid(cdiv(R, 16 * FN), cdiv(p, 64 * FM), nb);
     const int ldk = bf3_ldk(p);
     if (p % 4 == 0 && ((uintptr_t)A & 15) == 0)
-        hipLaunchKernelGGL((k_bgemm_bf3<FN, true, Epi>), grid, dim3(256), 0, s, p, R, A, Vp, ldk, epi);
+        hipLaunchKernelGGL((k_bgemm_bf3<FN, FM, true, Epi>), grid, dim3(256), 0, s, p, R, A, Vp, ldk, epi);
     else
-        hipLaunchKernelGGL((k_bgemm_bf3<FN, false, Epi>), grid, dim3(256), 0, s, p, R, A, Vp, ldk, epi);
+        hipLaunchKernelGGL((k_bgemm_bf3<FN, FM, false, Epi>), grid, dim3(256), 0, s, p, R, A, Vp, ldk, epi);
     UOI_LAUNCH_CHECK();
 }
 
