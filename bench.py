@@ -56,7 +56,7 @@ COPY_BYTES = 1 << 30
 # kstat slot -> (kernel name in profiles, sources whose change voids a stored traffic figure)
 CSRC = os.path.join("paper_1808_06992_amd", "csrc")
 KERNELS = {
-    "admm32": ("uoi::k_bgemm_bf3<N, true, uoi::AdmmEpiBf3<N> >", ["bgemm.hpp", "admm.hip", "common.hpp"]),
+    "admm32": ("uoi::k_bgemm_bf3<N, N, true, uoi::AdmmEpiBf3<N> >", ["bgemm.hpp", "admm.hip", "common.hpp"]),
     "admm64": ("uoi::k_bgemm<double, 1, N, uoi::AdmmEpi<double, 1, N> >", ["bgemm.hpp", "admm.hip", "common.hpp"]),
     "plain": ("uoi::k_admm_plain", ["admm.hip", "common.hpp"]),
     "gram": ("uoi::k_gram_f64<0, true>", ["gram.hip", "common.hpp"]),
@@ -81,6 +81,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-var", action="store_true",
                     help="skip the UoI_VAR fits (p192 T10000 and p1000 T20000, rho 1 and rho scaled to the data)")
+    ap.add_argument("--var-only", action="store_true",
+                    help="run only the UoI_VAR fits and print their results as one JSON line {\"var\": ...} "
+                         "(for profiling them on their own; not the benchmark line)")
     ap.add_argument("--cpu-boots", type=int, default=48,
                     help="bootstraps of the CPU oracle sample (B1 = B2 = this)")
     ap.add_argument("--mlp-seeds", type=int, default=4, help="design seeds of the network's training set")
@@ -396,6 +399,10 @@ def main():
         sys.exit(f"unknown variant {a.variant}; choose from {sorted(V)}")
     if a.copy_calibration:
         copy_calibration(torch)
+    if a.var_only:
+        log = lambda s: print(f"[bench] {s}", file=sys.stderr, flush=True)  # noqa: E731
+        print(json.dumps({"var": var_fits(api, torch, synth, log)}), flush=True)
+        return
     pr = synth.lasso_toeplitz(0)
     X = torch.as_tensor(pr.X).cuda()
     y = torch.as_tensor(pr.y).cuda()
