@@ -170,9 +170,9 @@ inline void run_bgemm(hipStream_t s, int nb, int p, int R, const T *A, const T *
 // a 32-deep step cost about a third of the eight float32 16x16x4 steps they
 // replace, which leaves the float32 ADMM iteration bound by reading A.
 //
-// Layout as k_bgemm (4 waves x 16 rows, 16*FN columns, KC = 32): lane (lr, lk)
-// reads eight entries of row i = i_base + lr of A (= column i, by symmetry) as
-// two 16-byte loads and splits them in registers.  V arrives
+// Layout as k_bgemm (4 waves x 16 FM rows, 16*FN columns, KC = 32): lane (lr, lk)
+// reads eight entries of row i = i_base + 16 a + lr of A (= column i, by
+// symmetry; a < FM) as two 16-byte loads and splits them in registers.  V arrives
 // already split, as three bfloat16 planes Vp[b][part][r][k] with k contiguous
 // and rows k >= p zero up to bf3_ldk(p) (the producing epilogue writes them; it
 // splits each element once instead of once per row block); a chunk is copied to
