@@ -334,6 +334,8 @@ __global__ __launch_bounds__(256) void k_ols_mid(int p, int pe, int R, int W,
     // backward solve L' x = y with y = row s of the factor, in blocks of 32 from the end
     for (int t = tid; t < s; t += 256) xv[t] = L[(size_t)t * ld + s];
     __syncthreads();
+    constexpr int LB = 33;
+    double *Lb = Pn;  // (the panel buffer is free now) Lb[u][j] = L[t0 + u][t0 + j], u > j, and the diagonal at u = j
     for (int t1 = s; t1 > 0; t1 -= 32) {
         const int t0 = max(0, t1 - 32);
         {   // xv[t] -= sum_{i >= t1} L[i][t] x_i for t in [t0, t1)
@@ -351,21 +353,33 @@ __global__ __launch_bounds__(256) void k_ols_mid(int p, int pe, int R, int W,
                 }
             red[g][tt] = part;
         }
+        // the diagonal block into LDS (column j of the factor holds rows j.. contiguously)
+        for (int q = tid; q < 32 * 32; q += 256) {
+            const int j = q >> 5, u = q & 31;
+            const bool in = t0 + u < t1 && t0 + j < t1 && u >= j;
+            Lb[u * LB + j] = in ? L[(size_t)(t0 + j) * ld + t0 + u] : 0.0;
+        }
         __syncthreads();
-        if (tid < 64) {  // one wave: the diagonal block, sequentially from its end
-            const int tt = tid & 31;
-            if (tid < 32 && t0 + tt < t1) {
+        if (tid < 64) {
+            // one wave, lane j holding x_{t0+j}: from the block's end, x_t is final
+            // once the columns after it are applied; it is divided by L[t][t] and
+            // broadcast, and every row j < t subtracts L[t][j] x_t
+            const int j = tid & 31;
+            double xr = 0.0;
+            if (tid < 32 && t0 + j < t1) {
                 double sacc = 0.0;
-                for (int g = 0; g < 8; ++g) sacc += red[g][tt];
-                xv[t0 + tt] -= sacc;
+                for (int g = 0; g < 8; ++g) sacc += red[g][j];
+                xr = xv[t0 + j] - sacc;
             }
-            for (int t = t1 - 1; t >= t0; --t) {
-                // x_t = (x_t - sum_{t < i < t1} L[i][t] x_i) / L[t][t]
-                const int i = t + 1 + tid;
-                double v = (tid < 32 && i < t1) ? L[(size_t)t * ld + i] * xv[i] : 0.0;
-                v = wave_sum(v);
-                if (tid == 0) xv[t] = (xv[t] - v) / L[(size_t)t * ld + t];
+            for (int u = t1 - 1 - t0; u >= 0; --u) {
+                const long long xb = __double_as_longlong(xr);
+                const int lo = __builtin_amdgcn_readlane((int)xb, u);
+                const int hi = __builtin_amdgcn_readlane((int)(xb >> 32), u);
+                const double xt = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo) / Lb[u * LB + u];
+                if (j == u) xr = xt;
+                else if (j < u) xr = fma(-Lb[u * LB + j], xt, xr);
             }
+            if (tid < 32 && t0 + j < t1) xv[t0 + j] = xr;
         }
         __syncthreads();
     }
