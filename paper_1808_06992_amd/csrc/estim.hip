@@ -54,14 +54,25 @@ __global__ void k_popcount(int R, int W, const uint64_t *__restrict__ supp, int3
 // List the members of support r into idx (LDS); returns the size.
 __device__ int support_members(const uint64_t *__restrict__ sw, int W, int *idx) {
     __shared__ int woff[1025];
-    // word offsets by a serial scan over at most W words (W <= 1024 checked on the host)
-    if (threadIdx.x == 0) {
-        int a = 0;
-        for (int w = 0; w < W; ++w) {
-            woff[w] = a;
-            a += __popcll(sw[w]);
+    // word offsets (W <= 1024 checked on the host): wave 0 loads 64 words at a time,
+    // all in flight, and prefix-sums their popcounts across the wave
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        int base = 0;
+        for (int w0 = 0; w0 < W; w0 += 64) {
+            const int w = w0 + lane;
+            const uint64_t x = sw[min(w, W - 1)];  // clamped: the count is masked below
+            const int c = w < W ? __popcll(x) : 0;
+            int incl = c;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(incl, o);
+                if (lane >= o) incl += y;
+            }
+            if (w < W) woff[w] = base + incl - c;
+            base += __shfl(incl, 63);
         }
-        woff[W] = a;
+        if (lane == 0) woff[W] = base;
     }
     __syncthreads();
     for (int w = threadIdx.x; w < W; w += blockDim.x) {
