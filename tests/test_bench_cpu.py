@@ -31,8 +31,22 @@ def test_roofline_hbm_bound_slot():
     assert r["traffic"] is None  # no counter record for that workload
 
 
-def test_stored_traffic_follows_the_sources():
-    # the committed Gram record carries the digest of its current sources
-    t = bench.stored_traffic("gram")
-    assert t is not None and t > 1e9
-    assert bench.stored_traffic("gram", "var_p1000_T20000") is None
+def test_stored_traffic_follows_the_sources(tmp_path, monkeypatch):
+    """A committed counter record counts only while the kernel's sources hash to
+    the digest it was taken on."""
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    (prof / "traffic_gram_w.txt").write_text("# header\nsources_sha256: abc123\ntraffic_bytes_per_launch: 4096\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "sources_digest", lambda files: "abc123")
+    assert bench.stored_traffic("gram", "w") == 4096.0
+    monkeypatch.setattr(bench, "sources_digest", lambda files: "changed")
+    assert bench.stored_traffic("gram", "w") is None
+    assert bench.stored_traffic("gram", "no_such_workload") is None
+
+
+def test_committed_records_are_current_or_void():
+    # the committed records either match their sources or are reported as null
+    for slot in ("gram", "admm32"):
+        t = bench.stored_traffic(slot)
+        assert t is None or t > 1e8
