@@ -778,17 +778,17 @@ struct AdmmWork {
     // float32 phase
     float *M32, *h32, *z32, *u32;
     __bf16 *vp0, *vp1;  // float32 phase: v as bfloat16 planes [nb][3][R][ldk]
-    int fm32;           // row blocks per wave of the float32 product (1 or 2)
+    int fm32, fm64;     // row blocks per wave of the float32 / float64 products (1 or 2)
     double *z64tmp;
 };
 
-// Products with more than one column tile may take two row blocks per wave
-// (the autotuner times both).
+// Products with more than one column tile may take two row blocks per wave,
+// float32 and float64 alike (the autotuner times both).
 inline bool offer_fm2(const AdmmProblem &P) { return P.R > 64 && P.p > 64; }
 
 AdmmWork carve(const AdmmProblem &P, int precision, int solver, Arena &ar) {
     AdmmWork w{};
-    w.fm32 = 1;
+    w.fm32 = w.fm64 = 1;
     size_t np2 = (size_t)P.nb * P.p * P.p, nst = (size_t)P.nb * P.p * P.R;
     w.M = ar.take<double>(np2);
     w.h = ar.take<double>((size_t)P.nb * P.p * P.pe);
@@ -839,9 +839,15 @@ static void check_launch(hipStream_t s, const AdmmProblem &P, const AdmmWork &w,
     if (estimate || zero) {
     } else if (std::is_same<T, double>::value) {
         UOI_DISPATCH_FN_RT(P.fn64, {
-            KktEpi<double, 1, FN> epi{P.C, (const double *)z, w.state, P.lam, w.vmax, P.p, P.R, P.pe,
-                                      only_active};
-            run_bgemm<double, 1, FN>(s, P.nb, P.p, P.R, P.G, (const double *)z, epi);
+            if (w.fm64 == 2) {
+                KktEpi<double, 2, FN> epi{P.C, (const double *)z, w.state, P.lam, w.vmax, P.p, P.R, P.pe,
+                                          only_active};
+                run_bgemm<double, 2, FN>(s, P.nb, P.p, P.R, P.G, (const double *)z, epi);
+            } else {
+                KktEpi<double, 1, FN> epi{P.C, (const double *)z, w.state, P.lam, w.vmax, P.p, P.R, P.pe,
+                                          only_active};
+                run_bgemm<double, 1, FN>(s, P.nb, P.p, P.R, P.G, (const double *)z, epi);
+            }
         });
     } else {
         // float32 z: widen to float64 first so the product is the float64 Gram times z
@@ -850,8 +856,13 @@ static void check_launch(hipStream_t s, const AdmmProblem &P, const AdmmWork &w,
                            w.v0);
         UOI_LAUNCH_CHECK();
         UOI_DISPATCH_FN_RT(P.fn64, {
-            KktEpi<double, 1, FN> epi{P.C, w.v0, w.state, P.lam, w.vmax, P.p, P.R, P.pe, only_active};
-            run_bgemm<double, 1, FN>(s, P.nb, P.p, P.R, P.G, w.v0, epi);
+            if (w.fm64 == 2) {
+                KktEpi<double, 2, FN> epi{P.C, w.v0, w.state, P.lam, w.vmax, P.p, P.R, P.pe, only_active};
+                run_bgemm<double, 2, FN>(s, P.nb, P.p, P.R, P.G, w.v0, epi);
+            } else {
+                KktEpi<double, 1, FN> epi{P.C, w.v0, w.state, P.lam, w.vmax, P.p, P.R, P.pe, only_active};
+                run_bgemm<double, 1, FN>(s, P.nb, P.p, P.R, P.G, w.v0, epi);
+            }
         });
     }
     int ns = P.nb * P.R;
@@ -928,9 +939,15 @@ static int sweep(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T
                     if (w.fm32 == 2) run_bgemm_bf3<FN, 2>(st, P.nb, P.p, P.R, M, pin, epi);
                     else run_bgemm_bf3<FN, 1>(st, P.nb, P.p, P.R, M, pin, epi);
                 } else {
-                    AdmmEpi<T, 1, FN> epi{h, z, u, vout, w.state, P.lam, P.p, P.R, P.pe, (T)P.rho,
-                                          (T)(1.0 / P.rho), (T)P.relax};
-                    run_bgemm<T, 1, FN>(st, P.nb, P.p, P.R, M, vin, epi);
+                    if (w.fm64 == 2) {
+                        AdmmEpi<T, 2, FN> epi{h, z, u, vout, w.state, P.lam, P.p, P.R, P.pe, (T)P.rho,
+                                              (T)(1.0 / P.rho), (T)P.relax};
+                        run_bgemm<T, 2, FN>(st, P.nb, P.p, P.R, M, vin, epi);
+                    } else {
+                        AdmmEpi<T, 1, FN> epi{h, z, u, vout, w.state, P.lam, P.p, P.R, P.pe, (T)P.rho,
+                                              (T)(1.0 / P.rho), (T)P.relax};
+                        run_bgemm<T, 1, FN>(st, P.nb, P.p, P.R, M, vin, epi);
+                    }
                 }
             });
         }
@@ -945,7 +962,7 @@ static int sweep(hipStream_t s, const AdmmProblem &P, const AdmmWork &w, const T
             GraphKey key;
             key.add(sizeof(T)).add(par).add(n).add(P.fn32).add(P.fn64).add(P.nb).add(P.p).add(P.R).add(P.pe)
                 .add(M).add(h).add(z)
-                .add(u).add(va).add(vb).add(w.vp0).add(w.vp1).add(w.fm32).add(w.state).add(P.lam).add(w.vmax).add(w.rmax)
+                .add(u).add(va).add(vb).add(w.vp0).add(w.vp1).add(w.fm32).add(w.fm64).add(w.state).add(P.lam).add(w.vmax).add(w.rmax)
                 .add(P.rho).add(P.relax);
             graph_launch(s, key, [&](hipStream_t cs) { issue(cs, par, n); });
         } else {
@@ -1173,11 +1190,14 @@ void admm_solve(hipStream_t s, const AdmmProblem &P0, int precision, int solver,
     // re-read M less often, more tiles give more workgroups; the tuner decides.  The
     // accumulation order of every output, and the epilogue's rounding (explicit
     // fused multiply-adds), are the same for every width, so the autotuner times
-    // them on the live operands: the float32 iteration with its real epilogue
-    // writing a scratch copy of the state, the float64 one as the bare product.
-    // With more than one column tile, the float32 candidates come twice: one row
-    // block per wave (candidates 0 .. n - 1), then two (n .. 2n - 1; the same
-    // accumulation order, so the same results).  The choice sets w.fm32.
+    // them on the live operands, each iteration with its real epilogue writing
+    // scratch state (float32: into the idle float64 buffer; float64: into the
+    // ping-pong buffers, which the refresh after the choice overwrites).  The
+    // float64 choice is made with every solve active (before the float64 sweep,
+    // or after the parked solves are released).
+    // With more than one column tile, the candidates come twice: one row block per
+    // wave (candidates 0 .. n - 1), then two (from n on; the same accumulation
+    // order, so the same results).  The choice sets w.fm32 or w.fm64.
     auto pick_fn = [&](bool f32) -> int {
         std::vector<int> cand, fm;
         for (int f = 1; f <= 4; ++f) {
@@ -1190,7 +1210,7 @@ void admm_solve(hipStream_t s, const AdmmProblem &P0, int precision, int solver,
             if (!dominated) cand.push_back(f);
         }
         fm.assign(cand.size(), 1);
-        if (f32 && offer_fm2(P)) {
+        if (offer_fm2(P)) {
             const size_t n0 = cand.size();
             for (size_t c = 0; c < n0; ++c) {
                 cand.push_back(cand[c]);
@@ -1201,7 +1221,7 @@ void admm_solve(hipStream_t s, const AdmmProblem &P0, int precision, int solver,
                                 "/p" + std::to_string(P.p) + "/R" + std::to_string(P.R);
         const int nc = (int)cand.size();
         auto chosen = [&](int c) {
-            if (f32) w.fm32 = fm[c];
+            (f32 ? w.fm32 : w.fm64) = fm[c];
             return cand[c];
         };
         if (!P.tune || nc == 1) return chosen(std::min(std::max(tune_lookup(key, 0), 0), nc - 1));
@@ -1217,8 +1237,16 @@ void admm_solve(hipStream_t s, const AdmmProblem &P0, int precision, int solver,
                     if (fm[c] == 2) run_bgemm_bf3<FN, 2>(s, P.nb, P.p, P.R, w.M32, w.vp0, e);
                     else run_bgemm_bf3<FN, 1>(s, P.nb, P.p, P.R, w.M32, w.vp0, e);
                 } else {
-                    StoreEpi<double, 1, FN> e{w.v1, P.p, P.R};
-                    run_bgemm<double, 1, FN>(s, P.nb, P.p, P.R, w.M, out.z, e);
+                    // (z in v0, u and the next v both in v1: scratch)
+                    if (fm[c] == 2) {
+                        AdmmEpi<double, 2, FN> e{w.h, w.v0, w.v1, w.v1, w.state, P.lam, P.p, P.R, P.pe, P.rho,
+                                                 1.0 / P.rho, P.relax};
+                        run_bgemm<double, 2, FN>(s, P.nb, P.p, P.R, w.M, out.z, e);
+                    } else {
+                        AdmmEpi<double, 1, FN> e{w.h, w.v0, w.v1, w.v1, w.state, P.lam, P.p, P.R, P.pe, P.rho,
+                                                 1.0 / P.rho, P.relax};
+                        run_bgemm<double, 1, FN>(s, P.nb, P.p, P.R, w.M, out.z, e);
+                    }
                 }
             });
         }, 5);
@@ -1303,8 +1331,8 @@ void admm_solve(hipStream_t s, const AdmmProblem &P0, int precision, int solver,
         // widen the state and finish parked / active solves in float64
         hipLaunchKernelGGL(k_f32_to_f64, dim3(cdiv(nst, 256)), dim3(256), 0, s, nst, w.z32, out.z);
         hipLaunchKernelGGL(k_f32_to_f64, dim3(cdiv(nst, 256)), dim3(256), 0, s, nst, w.u32, out.u);
-        P.fn64 = pick_fn(false);
         hipLaunchKernelGGL(k_unpark, dim3(cdiv(ns, 256)), dim3(256), 0, s, (size_t)ns, w.state);
+        P.fn64 = pick_fn(false);
         hipLaunchKernelGGL(k_refresh_v<double>, dim3(cdiv(nst, 256)), dim3(256), 0, s, nst, out.z,
                            out.u, w.v0, w.v1);
         UOI_LAUNCH_CHECK();
