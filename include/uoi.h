@@ -95,7 +95,8 @@ enum {
                                   named by the environment variable UOI_TUNE_FILE) or the
                                   defaults.  By default the library's autotuner times, on
                                   the first call of each problem shape, the candidates of
-                                  the ADMM products' column-tile width and of the factor's
+                                  the ADMM products' tile shape (columns, and rows per
+                                  wave above 64 solves per Gram) and of the factor's
                                   matrices per pass on the live operands (the candidates
                                   give identical results) and keeps the fastest           */
 
